@@ -1,0 +1,384 @@
+"""Pins of the oracle's DGSEM operator against what the method fixes (CPU only).
+
+* free-stream preservation (paper Sec. 2.2 runs a uniform state on a periodic
+  Cartesian mesh; a constant state must give a zero right-hand side);
+* discrete conservation on periodic meshes (telescoping of the surface terms);
+* kinetic-energy preservation of the Kennedy-Gruber split form with central
+  surface flux and constant pressure (summation-by-parts telescoping);
+* exactness of the BR1 lifting for continuous piecewise polynomials of degree <= N;
+* equivariance under a joint permutation of (x, y, z) and (u, v, w);
+* reduction of the 3-D operator to a 1-D one for x-only data;
+* physics identities of the two-point and surface fluxes;
+* order-(N+1) convergence against a manufactured Navier-Stokes solution and
+  convergence of the steady wall residual of compressible Poiseuille flow.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import physics as ph
+from oracle.basis import lgl
+from oracle.dgsem import kinetic_energy, lift, rhs, rk_step
+from oracle.mesh import Mesh, uniform_faces
+
+from _cases import channel_mesh, gas, random_faces, random_state, state_from_prims
+
+TWO_PI = 2 * math.pi
+
+
+def _periodic_stretched(N, n, seed=0):
+    rng = np.random.default_rng(seed)
+    faces = tuple(random_faces(k, 0.0, TWO_PI * (1 + 0.2 * d), rng) for d, k in enumerate(n))
+    return Mesh(N, faces)
+
+
+# ------------------------------------------------------------------ physics
+
+def test_kg_flux_consistency_symmetry_and_kep():
+    rng = np.random.default_rng(1)
+    g = gas()
+    m = Mesh(2, (uniform_faces(2, 0, 1),) * 3)
+    A = ph.primitives(random_state(m, g.gamma, g.R, rng), g)
+    B = ph.primitives(random_state(m, g.gamma, g.R, rng), g)
+    for d in range(3):
+        fAA, fA = ph.kg_flux(A, A, d), ph.euler_flux(A, d)
+        for v in range(5):
+            assert torch.allclose(fAA[v], fA[v], rtol=1e-14, atol=1e-14)
+        fAB, fBA = ph.kg_flux(A, B, d), ph.kg_flux(B, A, d)
+        for v in range(5):
+            assert torch.allclose(fAB[v], fBA[v], rtol=0, atol=1e-15)
+        # Jameson's kinetic-energy-preservation condition: f_m = {{u}} f_rho + {{p}} e_d
+        for a in range(3):
+            want = 0.5 * (A.vel[a] + B.vel[a]) * fAB[0] + (0.5 * (A.p + B.p) if a == d else 0.0)
+            assert torch.allclose(fAB[1 + a], want, rtol=1e-14, atol=1e-14)
+
+
+def test_llf_consistency_and_dissipation_sign():
+    rng = np.random.default_rng(2)
+    g = gas()
+    m = Mesh(2, (uniform_faces(2, 0, 1),) * 3)
+    U = random_state(m, g.gamma, g.R, rng)
+    V = random_state(m, g.gamma, g.R, rng)
+    A, B = ph.primitives(U, g), ph.primitives(V, g)
+    for d in range(3):
+        F = ph.llf_flux(A, A, U, U, d, g)
+        for v in range(5):
+            assert torch.allclose(F[v], ph.euler_flux(A, d)[v], rtol=1e-14, atol=1e-14)
+        # the dissipative part is -lambda/2 (U_R - U_L) with lambda >= max |u_d| + c
+        F = ph.llf_flux(A, B, U, V, d, g)
+        Fc = ph.kg_flux(A, B, d)
+        lam = -(F[0] - Fc[0]) / (0.5 * (V[0] - U[0]))
+        assert torch.all(lam >= (A.vel[d].abs() + A.c(g)) - 1e-12)
+        assert torch.all(lam >= (B.vel[d].abs() + B.c(g)) - 1e-12)
+
+
+def test_primitives_and_viscous_stress_identities():
+    rng = np.random.default_rng(3)
+    g = gas(mu=0.3)
+    m = Mesh(2, (uniform_faces(2, 0, 1),) * 3)
+    U = random_state(m, g.gamma, g.R, rng)
+    P = ph.primitives(U, g)
+    # round trip: rebuild U from primitives by the ideal-gas relation
+    E = P.p / (g.gamma - 1) + 0.5 * P.rho * sum(x * x for x in P.vel)
+    assert torch.allclose(E, U[4], rtol=1e-14)
+    assert torch.allclose(P.T, P.p / (P.rho * g.R))
+    grad = [[torch.tensor(rng.standard_normal(m.shape)) for _ in range(3)] for _ in range(4)]
+    tau = [ph.viscous_flux(P.vel, grad, d, g)[1:4] for d in range(3)]
+    for a in range(3):
+        for b in range(3):
+            assert torch.allclose(tau[b][a], tau[a][b], rtol=1e-14, atol=1e-14)  # symmetric
+    assert torch.allclose(tau[0][0] + tau[1][1] + tau[2][2], torch.zeros(m.shape, dtype=torch.float64), atol=1e-13)  # traceless
+    # energy: u . tau_d + kappa dT/dx_d ; kappa = mu gamma R / ((gamma-1) Pr)
+    fv = ph.viscous_flux(P.vel, grad, 1, g)
+    want = sum(P.vel[a] * tau[1][a] for a in range(3)) + g.mu * g.gamma * g.R / ((g.gamma - 1) * g.Pr) * grad[3][1]
+    assert torch.allclose(fv[4], want, rtol=1e-13, atol=1e-13)
+    assert torch.all(fv[0] == 0)
+
+
+# ------------------------------------------------------------ free stream
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_free_stream_preservation_periodic_stretched(N):
+    g = gas(mu=0.05)
+    m = _periodic_stretched(N, (3, 2, 4), seed=N)
+    shape = m.shape
+    rho, u, v, w, p = 1.3, 0.4, -0.7, 0.25, 2.1
+    U = state_from_prims(torch.full(shape, rho, dtype=torch.float64), torch.full(shape, u, dtype=torch.float64), torch.full(shape, v, dtype=torch.float64),
+                         torch.full(shape, w, dtype=torch.float64), torch.full(shape, p, dtype=torch.float64), g.gamma)
+    L = rhs(U, m, g)
+    fscale = (rho * 1.0 + p + (U[4, 0, 0, 0, 0, 0, 0].item() + p)) * max(2.0 / np.diff(f).min() for f in m.faces)
+    assert L.abs().max().item() < 1e-13 * fscale
+
+
+def test_fluid_at_rest_between_isothermal_walls():
+    g = gas(mu=0.02, R=3.0)
+    m = channel_mesh(3, 2, 4, 2, T_wall=1.7)
+    shape = m.shape
+    p = 5.0
+    rho = p / (g.R * 1.7)
+    z = torch.zeros(shape, dtype=torch.float64)
+    U = state_from_prims(torch.full(shape, rho, dtype=torch.float64), z, z, z, torch.full(shape, p, dtype=torch.float64), g.gamma)
+    L = rhs(U, m, g)
+    assert L.abs().max().item() < 1e-12 * p * 20
+
+
+# ----------------------------------------------------------- conservation
+
+@pytest.mark.parametrize("N", [1, 3, 4])
+def test_conservation_periodic(N):
+    rng = np.random.default_rng(10 + N)
+    g = gas(mu=0.05)
+    m = _periodic_stretched(N, (3, 2, 3), seed=N)
+    U = random_state(m, g.gamma, g.R, rng)
+    L = rhs(U, m, g)
+    wq = m.quadrature_weights()
+    for v in range(5):
+        tot = (wq * L[v]).sum().item()
+        scale = (wq * L[v].abs()).sum().item()
+        assert abs(tot) < 1e-13 * scale, (v, tot, scale)
+
+
+def test_mass_conservation_with_walls():
+    rng = np.random.default_rng(7)
+    g = gas(mu=0.05)
+    m = channel_mesh(3, 2, 3, 2)
+    U = random_state(m, g.gamma, g.R, rng)
+    L = rhs(U, m, g)
+    wq = m.quadrature_weights()
+    tot = (wq * L[0]).sum().item()
+    assert abs(tot) < 1e-13 * (wq * L[0].abs()).sum().item()
+
+
+# ---------------------------------------------------------- kinetic energy
+
+@pytest.mark.parametrize("N", [2, 3, 7])
+def test_kinetic_energy_preservation_central_constant_pressure(N):
+    rng = np.random.default_rng(20 + N)
+    g = gas(mu=0.0)
+    m = _periodic_stretched(N, (2, 3, 2), seed=100 + N)
+    U = random_state(m, g.gamma, g.R, rng, const_p=True)
+    L = rhs(U, m, g, viscous=False, central_only=True)
+    wq = m.quadrature_weights()
+    rho = U[0]
+    vel = U[1:4] / rho
+    rate = (wq * ((vel * L[1:4]).sum(0) - 0.5 * (vel * vel).sum(0) * L[0])).sum().item()
+    scale = (wq * L.abs().sum(0)).sum().item()
+    assert abs(rate) < 1e-13 * scale, (rate, scale)
+    # the same state with Lax-Friedrichs dissipation does lose kinetic energy (sensitivity)
+    L2 = rhs(U, m, g, viscous=False, central_only=False)
+    rate2 = (wq * ((vel * L2[1:4]).sum(0) - 0.5 * (vel * vel).sum(0) * L2[0])).sum().item()
+    assert abs(rate2) > 1e-6 * scale
+
+
+# ------------------------------------------------------------------ lifting
+
+@pytest.mark.parametrize("N", [2, 3, 5])
+def test_lifting_exact_for_continuous_polynomials_periodic(N):
+    g = gas(R=2.0)
+    m = _periodic_stretched(N, (3, 2, 2), seed=30 + N)
+    Lx, Ly, Lz = (f[-1] for f in m.faces)
+    X, Y, Z = m.coords()
+    qu = (X - Lx / 2) ** 2 / 10
+    qv = (Y - Ly / 2) * (Z - Lz / 2) ** 2 / 50 * 0 + (Y - Ly / 2) ** 2 / 10
+    qw = (Z - Lz / 2) ** 2 / 20 + (X - Lx / 2) ** 2 / 30
+    T = 1.0 + (X - Lx / 2) ** 2 / 40 + (Z - Lz / 2) ** 2 / 40
+    rho = torch.full_like(X, 1.5)
+    U = state_from_prims(rho, qu, qv, qw, rho * g.R * T, g.gamma)
+    grad = lift(U, m, g)
+    exact = {
+        (0, 0): (X - Lx / 2) / 5, (1, 1): (Y - Ly / 2) / 5, (2, 2): (Z - Lz / 2) / 10,
+        (2, 0): (X - Lx / 2) / 15, (3, 0): (X - Lx / 2) / 20, (3, 2): (Z - Lz / 2) / 20,
+    }
+    for c in range(4):
+        for d in range(3):
+            want = exact.get((c, d), torch.zeros_like(X))
+            assert torch.allclose(grad[c][d], want, atol=1e-12, rtol=0), (c, d)
+
+
+def test_lifting_exact_with_isothermal_walls():
+    g = gas(R=1.0)
+    Tw = 1.3
+    m = channel_mesh(3, 2, 4, 2, T_wall=Tw)
+    X, Y, Z = m.coords()
+    u = 1.5 * (1 - Y ** 2)
+    T = Tw + 0.2 * (1 - Y ** 2)
+    z = torch.zeros_like(X)
+    U = state_from_prims(torch.ones_like(X), u, z, z, g.R * T, g.gamma)
+    grad = lift(U, m, g)
+    assert torch.allclose(grad[0][1], -3.0 * Y, atol=1e-12, rtol=0)
+    assert torch.allclose(grad[3][1], -0.4 * Y, atol=1e-12, rtol=0)
+    assert grad[0][0].abs().max() < 1e-12 and grad[3][2].abs().max() < 1e-12
+
+
+# ----------------------------------------------------------- equivariance
+
+def test_axis_permutation_equivariance():
+    """Cycle (x, y, z) -> (y, z, x) together with (u, v, w): Ut must cycle the same way."""
+    rng = np.random.default_rng(41)
+    g = gas(mu=0.03)
+    N = 3
+    m = _periodic_stretched(N, (2, 3, 4), seed=41)
+    U = random_state(m, g.gamma, g.R, rng)
+    L = rhs(U, m, g)
+    # new coordinates: x' = y, y' = z, z' = x  =>  field'[ez', ey', ex', k', j', i'] with
+    # ex' = ey, ey' = ez, ez' = ex (and node indices likewise)
+    m2 = Mesh(N, (m.faces[1], m.faces[2], m.faces[0]))
+
+    def perm(field):  # (nz, ny, nx, k, j, i) -> (nx, nz, ny, i, k, j)
+        return field.permute(2, 0, 1, 5, 3, 4)
+
+    U2 = torch.stack([perm(U[0]), perm(U[2]), perm(U[3]), perm(U[1]), perm(U[4])])
+    L2 = rhs(U2, m2, g)
+    Lp = torch.stack([perm(L[0]), perm(L[2]), perm(L[3]), perm(L[1]), perm(L[4])])
+    assert torch.allclose(L2, Lp, rtol=0, atol=1e-12 * L.abs().max().item())
+
+
+def test_one_dimensional_reduction():
+    rng = np.random.default_rng(42)
+    g = gas(mu=0.03)
+    N = 3
+    m1 = Mesh(N, (random_faces(3, 0, TWO_PI, rng), uniform_faces(1, 0, 1), uniform_faces(1, 0, 1)))
+    m3 = Mesh(N, (m1.faces[0], uniform_faces(2, 0, 2), uniform_faces(3, 0, 1.5)))
+    X1 = m1.coords()[0]
+    X3 = m3.coords()[0]
+
+    def state(X):
+        rho = 1 + 0.2 * torch.sin(X)
+        u = 0.3 + 0.2 * torch.cos(X)
+        v = 0.1 * torch.sin(2 * X)
+        p = 1 + 0.1 * torch.cos(X)
+        return state_from_prims(rho, u, v, torch.zeros_like(X), p, g.gamma)
+
+    L1 = rhs(state(X1), m1, g)
+    L3 = rhs(state(X3), m3, g)
+    ref = L1[:, 0, 0]  # (5, nx, k, j, i) x-only line data
+    for ez in range(3):
+        for ey in range(2):
+            for k in range(N + 1):
+                for j in range(N + 1):
+                    assert torch.allclose(L3[:, ez, ey, :, k, j, :], ref[:, :, 0, 0, :], atol=1e-12, rtol=0)
+
+
+# ---------------------------------------------------------------- MMS
+
+def _mms_source(g):
+    import sympy as sp
+    x, y, z, t = sp.symbols("x y z t", real=True)
+    rho = 2 + sp.Rational(1, 10) * sp.sin(x + y + z - t)
+    u = sp.Rational(3, 10) + sp.Rational(1, 10) * sp.sin(x - t) * sp.cos(y)
+    v = -sp.Rational(1, 5) + sp.Rational(1, 10) * sp.cos(y + z - t)
+    w = sp.Rational(1, 10) + sp.Rational(1, 10) * sp.sin(z + x)
+    p = 1 + sp.Rational(1, 10) * sp.cos(x + y - 2 * t)
+    gam, R, mu, Pr = sp.Float(g.gamma), sp.Float(g.R), sp.Float(g.mu), sp.Float(g.Pr)
+    E = p / (gam - 1) + rho * (u ** 2 + v ** 2 + w ** 2) / 2
+    T = p / (rho * R)
+    kap = mu * gam * R / ((gam - 1) * Pr)
+    vel = [u, v, w]
+    X = [x, y, z]
+    div = sum(sp.diff(vel[a], X[a]) for a in range(3))
+    tau = [[mu * (sp.diff(vel[a], X[b]) + sp.diff(vel[b], X[a])) - (sp.Rational(2, 3) * mu * div if a == b else 0)
+            for b in range(3)] for a in range(3)]
+    Uc = [rho, rho * u, rho * v, rho * w, E]
+    S = []
+    for c in range(5):
+        expr = sp.diff(Uc[c], t)
+        for d in range(3):
+            if c == 0:
+                F = rho * vel[d]
+            elif c <= 3:
+                F = rho * vel[c - 1] * vel[d] + (p if c - 1 == d else 0) - tau[c - 1][d]
+            else:
+                F = (E + p) * vel[d] - sum(vel[a] * tau[a][d] for a in range(3)) - kap * sp.diff(T, X[d])
+            expr = expr + sp.diff(F, X[d])
+        S.append(sp.lambdify((x, y, z, t), expr, "numpy"))
+    Ufun = [sp.lambdify((x, y, z, t), e, "numpy") for e in Uc]
+    return S, Ufun
+
+
+def _eval(fun, X, Y, Z, t):
+    val = fun(X.numpy(), Y.numpy(), Z.numpy(), t)
+    return torch.as_tensor(np.broadcast_to(val, X.shape).copy(), dtype=torch.float64)
+
+
+@pytest.mark.parametrize("N", [2, 3, 4])
+def test_manufactured_truncation_error_order_N(N):
+    """Semi-discrete residual L(U_ex) + S - dU_ex/dt at the nodes converges at rate N."""
+    g = gas(mu=0.02)
+    S, Uf = _mms_source(g)
+    errs = []
+    for n in (4, 8):
+        m = Mesh(N, (uniform_faces(n, 0, TWO_PI),) * 3)
+        X, Y, Z = m.coords()
+        U0 = torch.stack([_eval(f, X, Y, Z, 0.0) for f in Uf])
+        h = 1e-6
+        dUdt = (torch.stack([_eval(f, X, Y, Z, h) for f in Uf])
+                - torch.stack([_eval(f, X, Y, Z, -h) for f in Uf])) / (2 * h)
+        src = torch.stack([_eval(f, X, Y, Z, 0.0) for f in S])
+        r = rhs(U0, m, g, source=src) - dUdt
+        wq = m.quadrature_weights()
+        errs.append([math.sqrt((wq * r[v] ** 2).sum().item()) for v in range(5)])
+    for v in range(5):
+        eoc = math.log2(errs[0][v] / errs[1][v])
+        assert eoc > N - 0.35, (v, errs, eoc)
+
+
+@pytest.mark.slow
+def test_manufactured_solution_convergence():
+    """Solution error after RK integration with the manufactured source (N = 3).
+
+    The solution error tends to order N+1 (3.29-3.63 is observed on 4^3 -> 8^3
+    elements, pre-asymptotic); a dropped or mis-signed term gives order <= 1.
+    """
+    N = 3
+    g = gas(mu=0.02)
+    S, Uf = _mms_source(g)
+    T_end, nsteps = 0.5, 25
+    errs = []
+    for n in (4, 8):
+        m = Mesh(N, (uniform_faces(n, 0, TWO_PI),) * 3)
+        X, Y, Z = m.coords()
+        U0 = torch.stack([_eval(f, X, Y, Z, 0.0) for f in Uf])
+        src = lambda t: torch.stack([_eval(f, X, Y, Z, t) for f in S])  # noqa: E731
+        U = rk_step(U0, m, g, T_end / nsteps, nsteps, source_fn=src)
+        Uex = torch.stack([_eval(f, X, Y, Z, T_end) for f in Uf])
+        wq = m.quadrature_weights()
+        errs.append([math.sqrt((wq * (U[v] - Uex[v]) ** 2).sum().item()) for v in range(5)])
+    for v in range(5):
+        eoc = math.log2(errs[0][v] / errs[1][v])
+        assert eoc > N + 0.2, (v, errs, eoc)
+
+
+def _poiseuille_residual(N, ny, g, f=0.02, Tw=1.0, p=10.0, alpha=2.0):
+    m = channel_mesh(N, 1, ny, 1, T_wall=Tw, alpha=alpha)
+    X, Y, Z = m.coords()
+    Uc = f / (2 * g.mu)
+    u = Uc * (1 - Y ** 2)
+    T = Tw + g.mu * Uc ** 2 / (3 * g.kappa) * (1 - Y ** 4)
+    z = torch.zeros_like(X)
+    U = state_from_prims(p / (g.R * T), u, z, z, torch.full_like(X, p), g.gamma)
+    src = torch.stack([z, torch.full_like(X, f), z, z, f * u])
+    return rhs(U, m, g, source=src)
+
+
+@pytest.mark.parametrize("N", [4, 5])
+def test_poiseuille_is_a_discrete_steady_state(N):
+    """Compressible Poiseuille flow with body force f between isothermal walls.
+
+    u = U_c (1 - y^2), T = T_w + mu U_c^2 / (3 kappa) (1 - y^4), p const, rho = p / (R T),
+    source (0, f, 0, 0, f u).  For N >= 4 u and T are exactly representable, so
+    the wall lifting value, the wall viscous flux with interior gradients and the
+    interior BR1 fluxes must make the residual vanish to rounding.
+    """
+    g = gas(mu=0.05, R=1.0)
+    for ny in (2, 4):
+        L = _poiseuille_residual(N, ny, g)
+        assert L.abs().max().item() < 1e-11
+
+
+def test_poiseuille_residual_converges_when_T_is_not_representable():
+    g = gas(mu=0.05, R=1.0)
+    res = [_poiseuille_residual(3, ny, g, alpha=0.5)[4].abs().max().item() for ny in (4, 8, 16)]
+    assert all(math.log2(res[k] / res[k + 1]) > 1.8 for k in range(2)), res
