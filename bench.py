@@ -1,0 +1,224 @@
+"""Throughput of the split-form DGSEM RK step on one MI355X.
+
+Workload: Taylor-Green vortex at N = 7 on 32^3 periodic elements (16.8 M DOF,
+DOF = one LGL node), 1 % seeded velocity noise, FP64, the five-stage
+low-storage RK at CFL 0.5.  One "step" is one RK step: five stages, each a
+lifting kernel and a fused right-hand-side + RK-update kernel.
+
+Prints one JSON line.  `value` is ns per DOF per RK stage (FP64), i.e. the
+paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
+  roofline      the fused RHS/RK kernel's algorithmic HBM bytes per launch over
+                its mean launch time (HIP events on the launch stream) vs 8 TB/s;
+  cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
+  mixed         the same step in mixed precision (when requested / available);
+  adjoint       adjoint/forward time ratio (when available).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+METRIC = "ns per DOF per RK stage (FP64 vs mixed) at N=7; adjoint/forward time ratio"
+
+# algorithmic HBM bytes per DOF (8 B per FP64 value, 4 B per FP32 gradient)
+#   lift:       read U (5) + write grad (12)
+#   rhs+RK:     read U (5) + grad (12) + G (5, not on stage 1) + write G (5) + U' (5)
+BYTES = {
+    "fp64": {"lift": 40 + 96, "rk": 40 + 96 + 40 + 40 + 40, "rk_first": 40 + 96 + 40 + 40},
+    "mixed": {"lift": 40 + 48, "rk": 40 + 48 + 40 + 40 + 40, "rk_first": 40 + 48 + 40 + 40},
+}
+
+
+def _parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tgv_n7_32x32x32")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    return ap.parse_args()
+
+
+def time_steps(S, dt, steps, warmup):
+    import torch
+    S.rk_step(dt, warmup)
+    S.sync()
+    torch.cuda.synchronize()
+    S.timing_begin(steps * 10 + 4)
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(S.stream)
+    S.rk_step(dt, steps)
+    end.record(S.stream)
+    torch.cuda.synchronize()
+    S.sync()
+    ms = start.elapsed_time(end)
+    lift_ms, rk_ms, n_lift, n_rk = S.timing_end()
+    return ms, lift_ms, rk_ms, n_lift, n_rk
+
+
+def cpu_baseline(wl):
+    """The oracle (unchanged) on a periodic 16x16x8-element sample of the same
+    N = 7 Taylor-Green state, three RK steps, on the host's cores."""
+    import numpy as np
+    import torch
+
+    from oracle.dgsem import rk_step
+    from oracle.mesh import Mesh
+    from oracle.physics import Gas
+    from paper_2606_18927_amd import workloads
+
+    sub = workloads.Workload("tgv_n7_sample", "tgv", wl.N, (16, 16, 8), nsteps=3, noise=wl.noise,
+                             seed=wl.seed)
+    from oracle.basis import lgl
+    xi, _ = lgl(sub.N)
+    U, dt = workloads.make_state(sub, xi.numpy())
+    mesh = Mesh(sub.N, sub.faces(), bc=sub.bc, T_wall=sub.T_wall)
+    gas = Gas(sub.gamma, sub.R, sub.mu, sub.Pr)
+    Ut = torch.as_tensor(U)
+    t0 = time.perf_counter()
+    rk_step(Ut, mesh, gas, dt, sub.nsteps)
+    sec = time.perf_counter() - t0
+    ns = sec * 1e9 / (mesh.n_dof * sub.nsteps * 5)
+    return {"value": ns, "unit": "ns/DOF/stage", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"N=7 Taylor-Green, 16x16x8 periodic elements ({mesh.n_dof} DOF), "
+                      f"{sub.nsteps} RK steps, {sec:.1f} s wall, float64 torch CPU",
+            "host_cpu_count": os.cpu_count()}
+
+
+def triad_gbs():
+    import torch
+
+    from paper_2606_18927_amd import dgsem
+    n = 1 << 27
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        dgsem.stream_triad(b, c, 1.5, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 20
+    e0.record()
+    for _ in range(reps):
+        dgsem.stream_triad(b, c, 1.5, a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b, c
+    return 24.0 * n / sec / 1e9
+
+
+def run_precision(wl, U, dt, precision, steps, warmup):
+    import torch
+
+    from paper_2606_18927_amd import dgsem
+    S = dgsem.solver_for(wl, precision=precision)
+    Ud = torch.as_tensor(U.reshape(-1)).cuda()
+    S.set_state(Ud)
+    ms, lift_ms, rk_ms, n_lift, n_rk = time_steps(S, dt, steps, warmup)
+    dof = S.n_dof
+    stages = steps * 5
+    ns = ms * 1e6 / (dof * stages)
+    b = BYTES[precision]
+    rk_bytes = dof * (b["rk"] * (stages - steps) + b["rk_first"] * steps) / stages
+    rk_avg_s = rk_ms / 1e3 / n_rk
+    lift_avg_s = lift_ms / 1e3 / max(n_lift, 1)
+    res = {
+        "ns_per_dof_stage": ns, "ms_per_step": ms / steps, "dof": dof,
+        "rk_kernel_ms": rk_ms / n_rk, "lift_kernel_ms": lift_ms / max(n_lift, 1),
+        "rk_kernel_gbs": rk_bytes / rk_avg_s / 1e9,
+        "lift_kernel_gbs": dof * b["lift"] / lift_avg_s / 1e9,
+        "step_alg_gbs": dof * (b["lift"] * stages + b["rk"] * (stages - steps) + b["rk_first"] * steps)
+        / (ms / 1e3) / 1e9,
+        "rk_bytes_per_launch": rk_bytes,
+    }
+    del S
+    torch.cuda.empty_cache()
+    return res, Ud
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2606_18927_amd import dgsem, workloads
+
+    wl = workloads.WORKLOADS[args.workload]
+    xi, _ = dgsem.lgl(wl.N)
+    U, dt = workloads.make_state(wl, xi)
+    print(f"[bench] {wl.name}: {wl.n_dof} DOF, dt={dt:.4e}, steps={args.steps}, warmup={args.warmup}",
+          file=sys.stderr, flush=True)
+
+    fp64, Ud = run_precision(wl, U, dt, "fp64", args.steps, args.warmup)
+    print(f"[bench] fp64 {fp64['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
+    mixed = None
+    if not args.no_mixed:
+        try:
+            mixed, _ = run_precision(wl, U, dt, "mixed", args.steps, args.warmup)
+            print(f"[bench] mixed {mixed['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
+        except dgsem.DgsemError as e:
+            mixed = {"error": str(e)}
+    adjoint = None
+    triad = triad_gbs()
+    print(f"[bench] triad {triad:.0f} GB/s", file=sys.stderr, flush=True)
+    cpu = None if args.no_cpu else cpu_baseline(wl)
+
+    value = fp64["ns_per_dof_stage"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "ns/DOF/stage",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fp64["ms_per_step"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded Taylor-Green state + 1% velocity noise)",
+        "config": {"workload": wl.name, "N": wl.N, "elements": list(wl.nelem), "dof": wl.n_dof,
+                   "rk_stages_per_step": 5, "precision": "fp64"},
+        "dof_stage_per_s": 1e9 / value,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_rhs (fused RHS + RK stage)",
+            "achieved": fp64["rk_kernel_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": fp64["rk_kernel_gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel_ms": fp64["rk_kernel_ms"],
+            "bytes_per_launch": fp64["rk_bytes_per_launch"],
+            "lift_kernel_gbs": fp64["lift_kernel_gbs"],
+            "step_alg_gbs": fp64["step_alg_gbs"],
+            "step_frac": fp64["step_alg_gbs"] / HBM_PEAK_GBS,
+            "triad_gbs": triad,
+            "step_frac_of_triad": fp64["step_alg_gbs"] / triad,
+        },
+        "cpu_baseline": cpu,
+        "mixed": mixed,
+        "adjoint": adjoint,
+        "context_mi300a_pid_ns": {"range": [2.457, 4.260], "note": "paper Table 1, 32 APUs, N=7 free stream"},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

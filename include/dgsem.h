@@ -1,0 +1,168 @@
+/*
+ * dgsem.h -- C ABI of the MI355X (gfx950) split-form DGSEM Navier-Stokes operator.
+ *
+ * The library evaluates the semi-discrete right-hand side dU/dt = L(U) of the
+ * compressible Navier-Stokes equations on an axis-aligned tensor-product mesh
+ * of hexahedra with Legendre-Gauss-Lobatto (LGL) collocation (paper Sec. 2.2:
+ * split-form DG on LGL nodes) and advances it with the five-stage fourth-order
+ * low-storage Runge-Kutta scheme (paper Sec. 4).  The operator is:
+ *   BR1 lifting of the primitive gradients grad(u, v, w, T);
+ *   Kennedy-Gruber split-form flux-differencing volume integral;
+ *   local Lax-Friedrichs surface flux (Kennedy-Gruber central part) and the
+ *   BR1 central viscous surface flux, with periodic or isothermal no-slip
+ *   wall boundaries (paper Sec. 3-4: periodic and wall boundaries, ideal gas,
+ *   viscous fluxes);
+ *   strong-form surface-to-volume lifting and the affine Jacobian scaling.
+ *
+ * Conventions shared by every call
+ *   - A DOF is one collocation node of one element: n_dof = nx ny nz (N+1)^3.
+ *   - State layout (all device pointers, float64, caller owned, contiguous):
+ *       U[v][e][k][j][i],  v in (rho, rho u, rho v, rho w, E),
+ *       e = ex + nx (ey + ny ez),  i is the x node index and runs fastest.
+ *     A state therefore holds 5 n_dof doubles.
+ *   - Gradient layout (dg_eval_lift): grad[3 q + d][e][k][j][i], q in (u, v, w, T),
+ *     d in (x, y, z); 12 n_dof doubles.
+ *   - Every call is asynchronous on the HIP stream given to dg_init_mesh and
+ *     returns a dg_status; no exception crosses the ABI.  Device-side
+ *     failures (non-positive density or pressure, NaN) are reported by dg_sync.
+ *   - The library never allocates device memory: the caller provides the
+ *     workspace (dg_workspace_bytes, dg_bind_workspace).  A context is bound
+ *     to one stream and one device and is not thread-safe.
+ */
+#ifndef DGSEM_H
+#define DGSEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = 1,        /* invalid argument or mesh description                  */
+  DG_ESTATE = 2,        /* call order violated (e.g. no workspace bound yet)     */
+  DG_EHIP = 3,          /* a HIP runtime call failed (dg_last_error has the text) */
+  DG_ENONPHYS = 4,      /* a kernel saw rho <= 0, p <= 0 or a NaN (from dg_sync) */
+  DG_EUNSUPPORTED = 5   /* valid request that this build does not implement      */
+} dg_status;
+
+#define DG_BC_PERIODIC 0
+#define DG_BC_ISOTHERMAL_WALL 1
+
+#define DG_FP64 0
+#define DG_MIXED 1
+
+typedef struct dg_ctx dg_ctx;
+
+/* Mesh description.  faces[d] are host arrays of nelem[d] + 1 strictly
+ * increasing coordinates; they are copied by dg_init_mesh.  bc[d] applies to
+ * both ends of direction d.  N must be 3, 5 or 7 (templated kernels).       */
+typedef struct {
+  int N;
+  int nelem[3];
+  const double* faces[3];
+  int bc[3];
+  double T_wall;      /* wall temperature of DG_BC_ISOTHERMAL_WALL ends          */
+} dg_mesh_desc;
+
+/* Gas and scheme switches.  Viscosity is constant; the heat conductivity is
+ * kappa = mu gamma R / ((gamma - 1) Pr).                                     */
+typedef struct {
+  double gamma, R, mu, Pr;
+  int viscous;        /* 0: Euler fluxes only (no lifting), 1: Navier-Stokes      */
+  int precision;      /* DG_FP64, or DG_MIXED: FP32 lifting, volume and surface
+                         fluxes; FP64 state, primitive recovery, RK accumulation */
+  int central_only;   /* 1: drop the Lax-Friedrichs dissipation (test switch)     */
+} dg_physics;
+
+/* Library version string (static storage). */
+const char* dg_version(void);
+
+/* LGL nodes xi[0..N] and weights w[0..N] (host arrays, caller owned), the
+ * basis of the paper's Sec. 2.2 scheme.  Pure host computation, any N in 1..16. */
+dg_status dg_lgl(int N, double* xi, double* w);
+
+/* Validate the mesh and physics, build the host tables and create a context
+ * on `hip_stream` (a hipStream_t, NULL = default stream).  No device work.
+ * Errors: DG_EINVAL (null pointers, non-monotone faces, bad bc, gamma <= 1,
+ * R <= 0, mu < 0, Pr <= 0, empty mesh), DG_EUNSUPPORTED (N not in {3, 5, 7}).  */
+dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* hip_stream,
+                       dg_ctx** out);
+
+/* Bytes of device workspace the context needs.  with_adjoint != 0 adds the
+ * buffers of the VJP calls.                                                  */
+dg_status dg_workspace_bytes(const dg_ctx* ctx, int with_adjoint, size_t* bytes);
+
+/* Number of DOFs (nodes) of the mesh. */
+dg_status dg_n_dof(const dg_ctx* ctx, long long* n_dof);
+
+/* Bind caller-owned device memory (>= dg_workspace_bytes, 256-byte aligned)
+ * and upload the tables.  May be called again to rebind.                      */
+dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes, int with_adjoint);
+
+/* Copy a state (layout above) into the context and clear the RK register. */
+dg_status dg_set_state(dg_ctx* ctx, const double* U_dev);
+
+/* Copy the context's current state out. */
+dg_status dg_get_state(const dg_ctx* ctx, double* U_dev);
+
+/* Ut = L(U) (paper Sec. 2.2 semi-discrete operator).  U and Ut must not overlap.
+ * t is the physical time (no time-dependent terms in this build).            */
+dg_status dg_eval_rhs(dg_ctx* ctx, const double* U_dev, double* Ut_dev, double t);
+
+/* BR1 lifted gradients of (u, v, w, T) of U, layout above (FP64 contexts only). */
+dg_status dg_eval_lift(dg_ctx* ctx, const double* U_dev, double* grad_dev);
+
+/* Advance the context's state by nsteps steps of size dt of the five-stage
+ * low-storage RK scheme (paper Sec. 4): per stage s, G <- A_s G + dt L(U),
+ * U <- U + B_s G.  t is the time at the start.                               */
+dg_status dg_rk_step(dg_ctx* ctx, double t, double dt, int nsteps);
+
+/* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs.  Needs a
+ * workspace bound with_adjoint.  FP64 arithmetic.                            */
+dg_status dg_eval_rhs_vjp(dg_ctx* ctx, const double* U_dev, const double* lam_dev,
+                          double* Ubar_dev, double t);
+
+/* One RK step backwards: given U_n and lamU_np1 = dJ/dU_{n+1}, write
+ * lamU_n = dJ/dU_n (recomputes the five stage states internally).           */
+dg_status dg_rk_step_vjp(dg_ctx* ctx, const double* U_n_dev, double t, double dt,
+                         const double* lamU_np1_dev, double* lamU_n_dev);
+
+/* Volume-averaged kinetic energy J(U) = sum wJ |m|^2/(2 rho) / sum wJ with LGL
+ * quadrature, written to J_dev[0] (device double).                           */
+dg_status dg_kinetic_energy(dg_ctx* ctx, const double* U_dev, double* J_dev);
+
+/* dJ/dU of dg_kinetic_energy (Euclidean gradient w.r.t. nodal values). */
+dg_status dg_kinetic_energy_grad(dg_ctx* ctx, const double* U_dev, double* lam_dev);
+
+/* STREAM triad a[i] = b[i] + s c[i] over n doubles on hip_stream (device
+ * pointers, caller owned): the measured HBM ceiling the operator's achieved
+ * bandwidth is compared with.  Asynchronous; no context needed.             */
+dg_status dg_stream_triad(const double* b_dev, const double* c_dev, double s, double* a_dev,
+                          long long n, void* hip_stream);
+
+/* Kernel timing for measurement.  dg_timing_begin(ctx, max_launches) makes the
+ * following forward launches of the context record a HIP event on its stream
+ * after each kernel (up to max_launches kernels; events are created here).
+ * dg_timing_end waits for the stream and returns, per kernel class, the summed
+ * device time in milliseconds and the launch count: [0] lifting, [1] right-hand
+ * side / fused RK stage.  Errors: DG_EINVAL (bad arguments), DG_ESTATE (end
+ * without begin), DG_EHIP.                                                   */
+dg_status dg_timing_begin(dg_ctx* ctx, int max_launches);
+dg_status dg_timing_end(dg_ctx* ctx, double ms[2], int count[2]);
+
+/* Wait for the stream; report and clear the device status word. */
+dg_status dg_sync(dg_ctx* ctx);
+
+/* Text of the last error of this context (static per context). */
+const char* dg_last_error(const dg_ctx* ctx);
+
+/* Release the context (the workspace stays owned by the caller). */
+dg_status dg_free(dg_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGSEM_H */

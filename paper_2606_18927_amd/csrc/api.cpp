@@ -1,0 +1,453 @@
+// C ABI of the DGSEM operator (declared in include/dgsem.h): argument
+// validation, host tables, workspace partitioning and kernel dispatch.
+// No call allocates device memory; every device operation is enqueued on the
+// context's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dg_internal.hpp"
+
+namespace {
+
+// Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients
+// (the fourth-order low-storage RK of paper Sec. 4).
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                        -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0,
+                        -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+
+constexpr int kPartials = 1024;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+dg_status fail(dg_ctx* c, dg_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  return st;
+}
+
+dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return DG_OK;
+  return fail(c, DG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+struct Layout {
+  size_t D, w, s[3], status, partial, U0, U1, G, grad;
+  size_t stages, lamG, lamU, ubar, gbar, tmp;
+  size_t fwd_end, adj_end;
+};
+
+Layout layout(const dg_ctx* c) {
+  Layout L{};
+  const size_t NP = c->N + 1;
+  const size_t dof = static_cast<size_t>(c->n_dof);
+  const size_t state = 5 * dof * sizeof(double);
+  const size_t gbytes = 12 * dof * (c->phys.precision == DG_MIXED ? sizeof(float) : sizeof(double));
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  L.D = take(NP * NP * sizeof(double));
+  L.w = take(NP * sizeof(double));
+  for (int d = 0; d < 3; ++d) L.s[d] = take(c->nelem[d] * sizeof(double));
+  L.status = take(sizeof(int));
+  L.partial = take(kPartials * sizeof(double));
+  L.U0 = take(state);
+  L.U1 = take(state);
+  L.G = take(state);
+  L.grad = c->phys.viscous ? take(gbytes) : off;
+  L.fwd_end = off;
+  L.stages = take(5 * state);
+  L.lamG = take(state);
+  L.lamU = take(state);
+  L.ubar = take(state);
+  L.gbar = take(12 * dof * sizeof(double));
+  L.tmp = take(state);
+  L.adj_end = off;
+  return L;
+}
+
+dg::DevMesh dev_mesh(const dg_ctx* c) {
+  dg::DevMesh m{};
+  for (int d = 0; d < 3; ++d) {
+    m.n[d] = c->nelem[d];
+    m.bc[d] = c->bc[d];
+    m.s[d] = c->ds[d];
+  }
+  m.T_wall = c->T_wall;
+  m.nE = c->nE;
+  return m;
+}
+
+dg::DevPhys dev_phys(const dg_ctx* c) {
+  dg::DevPhys p{};
+  p.gamma = c->phys.gamma;
+  p.gm1 = c->phys.gamma - 1.0;
+  p.R = c->phys.R;
+  p.inv_R = 1.0 / c->phys.R;
+  p.mu = c->phys.mu;
+  p.kappa = c->phys.mu * c->phys.gamma * c->phys.R / ((c->phys.gamma - 1.0) * c->phys.Pr);
+  p.cv = c->phys.R / (c->phys.gamma - 1.0);
+  p.viscous = c->phys.viscous;
+  p.central = c->phys.central_only;
+  return p;
+}
+
+dg::DevBasis dev_basis(const dg_ctx* c) {
+  dg::DevBasis b{};
+  b.D = c->dD;
+  b.inv_w_end = 1.0 / c->w[0];
+  return b;
+}
+
+double inv_volume(const dg_ctx* c) {
+  double v = 1.0;
+  for (int d = 0; d < 3; ++d) v *= c->faces[d].back() - c->faces[d].front();
+  return 1.0 / v;
+}
+
+// Record the end of a timed launch of kernel class `cls`.
+void mark(dg_ctx* c, int cls) {
+  if (!c->timing) return;
+  const size_t k = c->event_class.size();
+  if (k >= c->events.size()) return;
+  if (hipEventRecord(c->events[k], c->stream) == hipSuccess) c->event_class.push_back(cls);
+}
+
+dg_status need_bound(dg_ctx* c) {
+  if (!c) return DG_EINVAL;
+  if (!c->bound) return fail(c, DG_ESTATE, "no workspace bound (dg_bind_workspace)");
+  return DG_OK;
+}
+
+// Lifting (if viscous) then the right-hand side of U into Ut.
+dg_status eval_rhs_into(dg_ctx* c, const double* U, double* Ut) {
+  const dg::DevMesh m = dev_mesh(c);
+  const dg::DevPhys p = dev_phys(c);
+  const dg::DevBasis b = dev_basis(c);
+  if (c->phys.viscous) {
+    dg_status st = hip_check(c, dg::launch_lift(c->N, c->phys.precision, m, p, b, U, c->grad, c->stream),
+                             "lift kernel");
+    if (st != DG_OK) return st;
+    mark(c, 0);
+  }
+  dg_status st = hip_check(c, dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->grad, Ut, c->dstatus,
+                                             c->stream),
+                           "rhs kernel");
+  if (st == DG_OK) mark(c, 1);
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dg_version(void) { return "dgsem-gfx950 0.1"; }
+
+dg_status dg_lgl(int N, double* xi, double* w) {
+  if (N < 1 || N > 16 || !xi || !w) return DG_EINVAL;
+  std::vector<double> x, ww;
+  dg::lgl_nodes_weights(N, x, ww);
+  std::memcpy(xi, x.data(), (N + 1) * sizeof(double));
+  std::memcpy(w, ww.data(), (N + 1) * sizeof(double));
+  return DG_OK;
+}
+
+dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* hip_stream,
+                       dg_ctx** out) {
+  if (!mesh || !phys || !out) return DG_EINVAL;
+  *out = nullptr;
+  if (mesh->N != 3 && mesh->N != 5 && mesh->N != 7) return DG_EUNSUPPORTED;
+  long long nE = 1;
+  for (int d = 0; d < 3; ++d) {
+    if (mesh->nelem[d] <= 0 || !mesh->faces[d]) return DG_EINVAL;
+    if (mesh->bc[d] != DG_BC_PERIODIC && mesh->bc[d] != DG_BC_ISOTHERMAL_WALL) return DG_EINVAL;
+    for (int i = 0; i < mesh->nelem[d]; ++i) {
+      const double a = mesh->faces[d][i], b = mesh->faces[d][i + 1];
+      if (!(b > a) || !std::isfinite(a) || !std::isfinite(b)) return DG_EINVAL;
+    }
+    nE *= mesh->nelem[d];
+  }
+  const long long nn = static_cast<long long>(mesh->N + 1) * (mesh->N + 1) * (mesh->N + 1);
+  if (nE > (1LL << 31) / 8 || nE * nn * 12 > (1LL << 40)) return DG_EINVAL;
+  if (!(phys->gamma > 1.0) || !(phys->R > 0.0) || !(phys->mu >= 0.0) || !(phys->Pr > 0.0))
+    return DG_EINVAL;
+  if (phys->precision != DG_FP64 && phys->precision != DG_MIXED) return DG_EINVAL;
+  if (mesh->bc[0] == DG_BC_ISOTHERMAL_WALL || mesh->bc[1] == DG_BC_ISOTHERMAL_WALL ||
+      mesh->bc[2] == DG_BC_ISOTHERMAL_WALL) {
+    if (!(mesh->T_wall > 0.0)) return DG_EINVAL;
+  }
+
+  dg_ctx* c = new (std::nothrow) dg_ctx();
+  if (!c) return DG_EINVAL;
+  c->N = mesh->N;
+  for (int d = 0; d < 3; ++d) {
+    c->nelem[d] = mesh->nelem[d];
+    c->faces[d].assign(mesh->faces[d], mesh->faces[d] + mesh->nelem[d] + 1);
+    c->bc[d] = mesh->bc[d];
+    c->s[d].resize(mesh->nelem[d]);
+    for (int i = 0; i < mesh->nelem[d]; ++i)
+      c->s[d][i] = 2.0 / (c->faces[d][i + 1] - c->faces[d][i]);
+  }
+  c->T_wall = mesh->T_wall;
+  c->phys = *phys;
+  c->phys.viscous = phys->viscous ? 1 : 0;
+  c->phys.central_only = phys->central_only ? 1 : 0;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->nE = nE;
+  c->nn = nn;
+  c->n_dof = nE * nn;
+  dg::lgl_nodes_weights(c->N, c->xi, c->w);
+  dg::lgl_diff_matrix(c->xi, c->D);
+  *out = c;
+  return DG_OK;
+}
+
+dg_status dg_workspace_bytes(const dg_ctx* ctx, int with_adjoint, size_t* bytes) {
+  if (!ctx || !bytes) return DG_EINVAL;
+  const Layout L = layout(ctx);
+  *bytes = with_adjoint ? L.adj_end : L.fwd_end;
+  return DG_OK;
+}
+
+dg_status dg_n_dof(const dg_ctx* ctx, long long* n_dof) {
+  if (!ctx || !n_dof) return DG_EINVAL;
+  *n_dof = ctx->n_dof;
+  return DG_OK;
+}
+
+dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adjoint) {
+  if (!c || !dev_ptr) return DG_EINVAL;
+  if (reinterpret_cast<uintptr_t>(dev_ptr) % kAlign != 0)
+    return fail(c, DG_EINVAL, "workspace must be 256-byte aligned");
+  const Layout L = layout(c);
+  const size_t need = with_adjoint ? L.adj_end : L.fwd_end;
+  if (bytes < need) return fail(c, DG_EINVAL, "workspace too small");
+  char* ws = static_cast<char*>(dev_ptr);
+  c->ws = ws;
+  c->ws_bytes = bytes;
+  c->dD = reinterpret_cast<double*>(ws + L.D);
+  c->dw = reinterpret_cast<double*>(ws + L.w);
+  for (int d = 0; d < 3; ++d) c->ds[d] = reinterpret_cast<double*>(ws + L.s[d]);
+  c->dstatus = reinterpret_cast<int*>(ws + L.status);
+  c->dpartial = reinterpret_cast<double*>(ws + L.partial);
+  c->n_partial = kPartials;
+  c->U[0] = reinterpret_cast<double*>(ws + L.U0);
+  c->U[1] = reinterpret_cast<double*>(ws + L.U1);
+  c->cur = 0;
+  c->G = reinterpret_cast<double*>(ws + L.G);
+  c->grad = c->phys.viscous ? static_cast<void*>(ws + L.grad) : nullptr;
+  if (with_adjoint) {
+    c->stages = reinterpret_cast<double*>(ws + L.stages);
+    c->lamG = reinterpret_cast<double*>(ws + L.lamG);
+    c->lamU = reinterpret_cast<double*>(ws + L.lamU);
+    c->ubar = reinterpret_cast<double*>(ws + L.ubar);
+    c->gbar = static_cast<void*>(ws + L.gbar);
+    c->tmp = reinterpret_cast<double*>(ws + L.tmp);
+  } else {
+    c->stages = c->lamG = c->lamU = c->ubar = c->tmp = nullptr;
+    c->gbar = nullptr;
+  }
+  c->adjoint_bound = with_adjoint != 0;
+  const size_t NP = c->N + 1;
+  dg_status st;
+  if ((st = hip_check(c, hipMemcpyAsync(c->dD, c->D.data(), NP * NP * sizeof(double),
+                                        hipMemcpyHostToDevice, c->stream), "upload D")) != DG_OK)
+    return st;
+  if ((st = hip_check(c, hipMemcpyAsync(c->dw, c->w.data(), NP * sizeof(double),
+                                        hipMemcpyHostToDevice, c->stream), "upload w")) != DG_OK)
+    return st;
+  for (int d = 0; d < 3; ++d)
+    if ((st = hip_check(c, hipMemcpyAsync(c->ds[d], c->s[d].data(), c->nelem[d] * sizeof(double),
+                                          hipMemcpyHostToDevice, c->stream), "upload s")) != DG_OK)
+      return st;
+  if ((st = hip_check(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), c->stream), "clear status")) != DG_OK)
+    return st;
+  if ((st = hip_check(c, hipMemsetAsync(c->G, 0, 5 * c->n_dof * sizeof(double), c->stream),
+                      "clear G")) != DG_OK)
+    return st;
+  // the host tables above live in the context, so the asynchronous copies may
+  // still be in flight after return; they complete before any later kernel.
+  c->bound = true;
+  return DG_OK;
+}
+
+dg_status dg_set_state(dg_ctx* c, const double* U) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U) return fail(c, DG_EINVAL, "null state");
+  c->cur = 0;
+  const size_t bytes = 5 * c->n_dof * sizeof(double);
+  if ((st = hip_check(c, hipMemcpyAsync(c->U[0], U, bytes, hipMemcpyDeviceToDevice, c->stream),
+                      "set_state copy")) != DG_OK)
+    return st;
+  return hip_check(c, hipMemsetAsync(c->G, 0, bytes, c->stream), "clear G");
+}
+
+dg_status dg_get_state(const dg_ctx* cc, double* U) {
+  dg_ctx* c = const_cast<dg_ctx*>(cc);
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U) return fail(c, DG_EINVAL, "null state");
+  return hip_check(c, hipMemcpyAsync(U, c->U[c->cur], 5 * c->n_dof * sizeof(double),
+                                     hipMemcpyDeviceToDevice, c->stream),
+                   "get_state copy");
+}
+
+dg_status dg_eval_rhs(dg_ctx* c, const double* U, double* Ut, double /*t*/) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U || !Ut || U == Ut) return fail(c, DG_EINVAL, "bad U/Ut pointers");
+  return eval_rhs_into(c, U, Ut);
+}
+
+dg_status dg_eval_lift(dg_ctx* c, const double* U, double* grad) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U || !grad) return fail(c, DG_EINVAL, "bad pointers");
+  if (c->phys.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "eval_lift: FP64 contexts only");
+  return hip_check(c, dg::launch_lift(c->N, DG_FP64, dev_mesh(c), dev_phys(c), dev_basis(c), U, grad,
+                                      c->stream),
+                   "lift kernel");
+}
+
+dg_status dg_rk_step(dg_ctx* c, double /*t*/, double dt, int nsteps) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(c, DG_EINVAL, "bad dt/nsteps");
+  const dg::DevMesh m = dev_mesh(c);
+  const dg::DevPhys p = dev_phys(c);
+  const dg::DevBasis b = dev_basis(c);
+  for (int n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < 5; ++s) {
+      const double* Uin = c->U[c->cur];
+      double* Uout = c->U[c->cur ^ 1];
+      if (c->phys.viscous) {
+        if ((st = hip_check(c, dg::launch_lift(c->N, c->phys.precision, m, p, b, Uin, c->grad, c->stream),
+                            "lift kernel")) != DG_OK)
+          return st;
+        mark(c, 0);
+      }
+      const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
+      if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, Uin, c->grad, c->G,
+                                                 Uout, stage, c->dstatus, c->stream),
+                          "rk stage kernel")) != DG_OK)
+        return st;
+      mark(c, 1);
+      c->cur ^= 1;
+    }
+  }
+  return DG_OK;
+}
+
+dg_status dg_eval_rhs_vjp(dg_ctx* c, const double*, const double*, double*, double) {
+  return fail(c, DG_EUNSUPPORTED, "eval_rhs_vjp not built yet");
+}
+
+dg_status dg_rk_step_vjp(dg_ctx* c, const double*, double, double, const double*, double*) {
+  return fail(c, DG_EUNSUPPORTED, "rk_step_vjp not built yet");
+}
+
+dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double* J) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U || !J) return fail(c, DG_EINVAL, "bad pointers");
+  return hip_check(c, dg::launch_kinetic_energy(c->N, dev_mesh(c), c->dw, U, c->dpartial, c->n_partial,
+                                                inv_volume(c), J, c->stream),
+                   "kinetic energy kernels");
+}
+
+dg_status dg_kinetic_energy_grad(dg_ctx* c, const double* U, double* lam) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U || !lam) return fail(c, DG_EINVAL, "bad pointers");
+  return hip_check(c, dg::launch_kinetic_energy_grad(c->N, dev_mesh(c), c->dw, U, inv_volume(c), lam,
+                                                     c->stream),
+                   "kinetic energy gradient kernel");
+}
+
+dg_status dg_stream_triad(const double* b, const double* cc, double s, double* a, long long n,
+                          void* hip_stream) {
+  if (!b || !cc || !a || n < 0) return DG_EINVAL;
+  return dg::launch_triad(b, cc, s, a, n, static_cast<hipStream_t>(hip_stream)) == hipSuccess
+             ? DG_OK
+             : DG_EHIP;
+}
+
+dg_status dg_timing_begin(dg_ctx* c, int max_launches) {
+  if (!c || max_launches <= 0) return DG_EINVAL;
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  c->events.clear();
+  c->event_class.clear();
+  if (c->event_start) (void)hipEventDestroy(c->event_start);
+  c->event_start = nullptr;
+  dg_status st = hip_check(c, hipEventCreate(&c->event_start), "event create");
+  if (st != DG_OK) return st;
+  c->events.resize(max_launches, nullptr);
+  for (auto& e : c->events)
+    if ((st = hip_check(c, hipEventCreate(&e), "event create")) != DG_OK) return st;
+  if ((st = hip_check(c, hipEventRecord(c->event_start, c->stream), "event record")) != DG_OK) return st;
+  c->timing = true;
+  return DG_OK;
+}
+
+dg_status dg_timing_end(dg_ctx* c, double ms[2], int count[2]) {
+  if (!c || !ms || !count) return DG_EINVAL;
+  if (!c->timing) return fail(c, DG_ESTATE, "dg_timing_end without dg_timing_begin");
+  c->timing = false;
+  dg_status st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+  if (st != DG_OK) return st;
+  ms[0] = ms[1] = 0.0;
+  count[0] = count[1] = 0;
+  hipEvent_t prev = c->event_start;
+  for (size_t k = 0; k < c->event_class.size(); ++k) {
+    float t = 0.0f;
+    if ((st = hip_check(c, hipEventElapsedTime(&t, prev, c->events[k]), "event elapsed")) != DG_OK) return st;
+    ms[c->event_class[k]] += t;
+    count[c->event_class[k]] += 1;
+    prev = c->events[k];
+  }
+  return DG_OK;
+}
+
+dg_status dg_sync(dg_ctx* c) {
+  if (!c) return DG_EINVAL;
+  dg_status st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize");
+  if (st != DG_OK || !c->bound) return st;
+  int flag = 0;
+  if ((st = hip_check(c, hipMemcpyAsync(&flag, c->dstatus, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                      "read status")) != DG_OK)
+    return st;
+  if ((st = hip_check(c, hipStreamSynchronize(c->stream), "stream synchronize")) != DG_OK) return st;
+  if (flag) {
+    if ((st = hip_check(c, hipMemsetAsync(c->dstatus, 0, sizeof(int), c->stream), "clear status")) != DG_OK)
+      return st;
+    return fail(c, DG_ENONPHYS, "non-physical state (rho <= 0, p <= 0 or NaN) seen by a kernel");
+  }
+  return DG_OK;
+}
+
+const char* dg_last_error(const dg_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+dg_status dg_free(dg_ctx* c) {
+  if (c) {
+    for (hipEvent_t e : c->events)
+      if (e) (void)hipEventDestroy(e);
+    if (c->event_start) (void)hipEventDestroy(c->event_start);
+  }
+  delete c;
+  return DG_OK;
+}
+
+}  // extern "C"

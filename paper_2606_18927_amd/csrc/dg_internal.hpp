@@ -1,0 +1,113 @@
+// Internal declarations shared by the host API and the HIP kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <string>
+#include <vector>
+
+#include "../../include/dgsem.h"
+
+namespace dg {
+
+constexpr int kMaxN = 7;
+constexpr int kMaxNP = kMaxN + 1;
+
+// Mesh data a kernel needs.  Every element is an axis-aligned box; its
+// metric scale along direction d is s_d = 2 / width_d (one table per direction).
+struct DevMesh {
+  int n[3];           // elements per direction (x, y, z)
+  int bc[3];          // DG_BC_PERIODIC or DG_BC_ISOTHERMAL_WALL
+  double T_wall;
+  const double* s[3]; // device tables of s_d per element index along d
+  long long nE;       // number of elements
+};
+
+// Gas constants and switches (FP64; kernels cast where they compute in FP32).
+struct DevPhys {
+  double gamma, gm1, R, inv_R, mu, kappa, cv;
+  int viscous, central;
+};
+
+// LGL tables of one N, held in device memory inside the workspace.
+struct DevBasis {
+  const double* D;    // D[i * NP + m] = l_m'(xi_i)
+  double inv_w_end;   // 1 / w_0 (= 1 / w_N)
+};
+
+// RK stage coefficients of one launch.
+struct Stage {
+  double A, B, dt;
+  int read_G;         // 0 on the first stage (A_1 = 0): G is not read
+};
+
+// Kernel launchers (fwd_kernels.hip).  grad is double* for DG_FP64 and
+// float* for DG_MIXED.
+hipError_t launch_lift(int N, int precision, const DevMesh& m, const DevPhys& p,
+                       const DevBasis& b, const double* U, void* grad, hipStream_t s);
+hipError_t launch_rhs(int N, int precision, const DevMesh& m, const DevPhys& p,
+                      const DevBasis& b, const double* U, const void* grad, double* Ut,
+                      int* status, hipStream_t s);
+hipError_t launch_rk_stage(int N, int precision, const DevMesh& m, const DevPhys& p,
+                           const DevBasis& b, const double* U, const void* grad, double* G,
+                           double* U_out, const Stage& st, int* status, hipStream_t s);
+
+// Reductions and elementwise kernels (aux_kernels.hip).
+hipError_t launch_kinetic_energy(int N, const DevMesh& m, const double* w, const double* U,
+                                 double* partial, int n_partial, double inv_vol, double* J,
+                                 hipStream_t s);
+hipError_t launch_kinetic_energy_grad(int N, const DevMesh& m, const double* w, const double* U,
+                                      double inv_vol, double* lam, hipStream_t s);
+hipError_t launch_triad(const double* b, const double* c, double s, double* a, long long n,
+                        hipStream_t st);
+
+// Host LGL construction (lgl.cpp): Newton on (1 - x^2) P_N'(x), barycentric D.
+void lgl_nodes_weights(int N, std::vector<double>& xi, std::vector<double>& w);
+void lgl_diff_matrix(const std::vector<double>& xi, std::vector<double>& D);
+
+}  // namespace dg
+
+struct dg_ctx {
+  int N = 0;
+  int nelem[3] = {0, 0, 0};
+  std::vector<double> faces[3];
+  int bc[3] = {0, 0, 0};
+  double T_wall = 1.0;
+  dg_physics phys{};
+  hipStream_t stream = nullptr;
+  long long nE = 0, nn = 0, n_dof = 0;
+
+  std::vector<double> xi, w, D, s[3];
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  bool adjoint_bound = false;
+  double* dD = nullptr;
+  double* dw = nullptr;
+  double* ds[3] = {nullptr, nullptr, nullptr};
+  int* dstatus = nullptr;
+  double* dpartial = nullptr;
+  int n_partial = 0;
+  double* U[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* G = nullptr;
+  void* grad = nullptr;
+  // adjoint buffers
+  double* stages = nullptr;   // 5 stage input states of one step
+  double* lamG = nullptr;
+  double* lamU = nullptr;
+  double* ubar = nullptr;     // per-node partial cotangent of the state
+  void* gbar = nullptr;       // cotangent of the lifted gradients
+  double* tmp = nullptr;      // one state of scratch
+
+  // measurement: one event after each timed launch (kernel class 0 = lift, 1 = rhs)
+  std::vector<hipEvent_t> events;
+  std::vector<int> event_class;
+  hipEvent_t event_start = nullptr;
+  bool timing = false;
+
+  std::string err;
+};

@@ -1,0 +1,269 @@
+"""ctypes binding of ``libdgsem.so`` (the C ABI of include/dgsem.h).
+
+Argument marshalling only: every step of the operator runs in the HIP kernels
+of the library.  Torch provides the device memory (states, workspace) and the
+stream.  The functions keep the C names without the ``dg_`` prefix.
+
+Loading fails loudly (``DgsemError``) when the library has not been built;
+there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgsem.so")
+
+DG_OK, DG_EINVAL, DG_ESTATE, DG_EHIP, DG_ENONPHYS, DG_EUNSUPPORTED = range(6)
+STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ESTATE", 3: "DG_EHIP", 4: "DG_ENONPHYS",
+                5: "DG_EUNSUPPORTED"}
+BC = {"periodic": 0, "wall": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+
+
+class DgsemError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int), ("nelem", ctypes.c_int * 3),
+                ("faces", ctypes.POINTER(ctypes.c_double) * 3), ("bc", ctypes.c_int * 3),
+                ("T_wall", ctypes.c_double)]
+
+
+class Physics(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("R", ctypes.c_double), ("mu", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("viscous", ctypes.c_int), ("precision", ctypes.c_int),
+                ("central_only", ctypes.c_int)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_SIGNATURES = {
+    "dg_version": (ctypes.c_char_p, []),
+    "dg_lgl": (_I, [_I, _P, _P]),
+    "dg_init_mesh": (_I, [ctypes.POINTER(MeshDesc), ctypes.POINTER(Physics), _P, ctypes.POINTER(_P)]),
+    "dg_workspace_bytes": (_I, [_P, _I, ctypes.POINTER(ctypes.c_size_t)]),
+    "dg_n_dof": (_I, [_P, ctypes.POINTER(ctypes.c_longlong)]),
+    "dg_bind_workspace": (_I, [_P, _P, ctypes.c_size_t, _I]),
+    "dg_set_state": (_I, [_P, _P]),
+    "dg_get_state": (_I, [_P, _P]),
+    "dg_eval_rhs": (_I, [_P, _P, _P, _D]),
+    "dg_eval_lift": (_I, [_P, _P, _P]),
+    "dg_rk_step": (_I, [_P, _D, _D, _I]),
+    "dg_eval_rhs_vjp": (_I, [_P, _P, _P, _P, _D]),
+    "dg_rk_step_vjp": (_I, [_P, _P, _D, _D, _P, _P]),
+    "dg_kinetic_energy": (_I, [_P, _P, _P]),
+    "dg_kinetic_energy_grad": (_I, [_P, _P, _P]),
+    "dg_stream_triad": (_I, [_P, _P, _D, _P, ctypes.c_longlong, _P]),
+    "dg_timing_begin": (_I, [_P, _I]),
+    "dg_timing_end": (_I, [_P, _P, _P]),
+    "dg_sync": (_I, [_P]),
+    "dg_last_error": (ctypes.c_char_p, [_P]),
+    "dg_free": (_I, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdgsem.so (once).  Raises DgsemError if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise DgsemError(DG_ESTATE, f"{LIB_PATH} not built: run python -m paper_2606_18927_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGNATURES)
+
+
+def version() -> str:
+    return lib().dg_version().decode()
+
+
+def lgl(N: int):
+    xi = np.zeros(N + 1)
+    w = np.zeros(N + 1)
+    st = lib().dg_lgl(N, xi.ctypes.data, w.ctypes.data)
+    if st != DG_OK:
+        raise DgsemError(st, "dg_lgl")
+    return xi, w
+
+
+def stream_triad(b: torch.Tensor, c: torch.Tensor, s: float, a: torch.Tensor):
+    st = lib().dg_stream_triad(b.data_ptr(), c.data_ptr(), s, a.data_ptr(), a.numel(),
+                               torch.cuda.current_stream(a.device).cuda_stream)
+    if st != DG_OK:
+        raise DgsemError(st, "dg_stream_triad")
+
+
+def _ptr(t: torch.Tensor, n: int, what: str) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what}: expected a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous float64 tensor")
+    if t.numel() != n:
+        raise ValueError(f"{what}: expected {n} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+@dataclass
+class MeshSpec:
+    N: int
+    faces: tuple               # three 1-D arrays
+    bc: tuple = ("periodic", "periodic", "periodic")
+    T_wall: float = 1.0
+
+    @property
+    def nelem(self):
+        return tuple(len(f) - 1 for f in self.faces)
+
+
+class Solver:
+    """One context of the operator on the current device and stream."""
+
+    def __init__(self, mesh: MeshSpec, gamma: float, R: float, mu: float, Pr: float, *,
+                 viscous: bool = True, precision: str = "fp64", central_only: bool = False,
+                 with_adjoint: bool = False, device=None):
+        L = lib()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream(self.device)
+        self.mesh = mesh
+        self._faces = [np.ascontiguousarray(f, dtype=np.float64) for f in mesh.faces]
+        desc = MeshDesc()
+        desc.N = mesh.N
+        for d in range(3):
+            desc.nelem[d] = len(self._faces[d]) - 1
+            desc.faces[d] = self._faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            desc.bc[d] = BC[mesh.bc[d]]
+        desc.T_wall = mesh.T_wall
+        phys = Physics(gamma, R, mu, Pr, 1 if viscous else 0, PRECISION[precision], 1 if central_only else 0)
+        ctx = _P()
+        st = L.dg_init_mesh(ctypes.byref(desc), ctypes.byref(phys), self.stream.cuda_stream, ctypes.byref(ctx))
+        if st != DG_OK:
+            raise DgsemError(st, "dg_init_mesh")
+        self._ctx = ctx
+        n = ctypes.c_longlong()
+        self._check(L.dg_n_dof(ctx, ctypes.byref(n)), "dg_n_dof")
+        self.n_dof = n.value
+        nbytes = ctypes.c_size_t()
+        self._check(L.dg_workspace_bytes(ctx, 1 if with_adjoint else 0, ctypes.byref(nbytes)), "dg_workspace_bytes")
+        self.workspace_bytes = nbytes.value
+        self._ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(L.dg_bind_workspace(ctx, aligned, nbytes.value, 1 if with_adjoint else 0),
+                    "dg_bind_workspace")
+
+    # -- helpers ------------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != DG_OK:
+            msg = lib().dg_last_error(self._ctx).decode() if getattr(self, "_ctx", None) else ""
+            raise DgsemError(st, f"{what}: {msg}")
+
+    def state_like(self) -> torch.Tensor:
+        return torch.empty(5 * self.n_dof, dtype=torch.float64, device=self.device)
+
+    def _state_ptr(self, U, what="U"):
+        return _ptr(U, 5 * self.n_dof, what)
+
+    # -- C ABI --------------------------------------------------------------
+    def set_state(self, U: torch.Tensor):
+        self._check(lib().dg_set_state(self._ctx, self._state_ptr(U)), "dg_set_state")
+
+    def get_state(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.state_like() if out is None else out
+        self._check(lib().dg_get_state(self._ctx, self._state_ptr(out, "out")), "dg_get_state")
+        return out
+
+    def eval_rhs(self, U: torch.Tensor, out: torch.Tensor | None = None, t: float = 0.0) -> torch.Tensor:
+        out = self.state_like() if out is None else out
+        self._check(lib().dg_eval_rhs(self._ctx, self._state_ptr(U), self._state_ptr(out, "Ut"), t),
+                    "dg_eval_rhs")
+        return out
+
+    def eval_lift(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty(12 * self.n_dof, dtype=torch.float64, device=self.device) if out is None else out
+        self._check(lib().dg_eval_lift(self._ctx, self._state_ptr(U), _ptr(out, 12 * self.n_dof, "grad")),
+                    "dg_eval_lift")
+        return out
+
+    def rk_step(self, dt: float, nsteps: int = 1, t: float = 0.0):
+        self._check(lib().dg_rk_step(self._ctx, t, dt, nsteps), "dg_rk_step")
+
+    def eval_rhs_vjp(self, U: torch.Tensor, lam: torch.Tensor, out: torch.Tensor | None = None,
+                     t: float = 0.0) -> torch.Tensor:
+        out = self.state_like() if out is None else out
+        self._check(lib().dg_eval_rhs_vjp(self._ctx, self._state_ptr(U), self._state_ptr(lam, "lam"),
+                                          self._state_ptr(out, "Ubar"), t), "dg_eval_rhs_vjp")
+        return out
+
+    def rk_step_vjp(self, U_n: torch.Tensor, dt: float, lam_np1: torch.Tensor,
+                    out: torch.Tensor | None = None, t: float = 0.0) -> torch.Tensor:
+        out = self.state_like() if out is None else out
+        self._check(lib().dg_rk_step_vjp(self._ctx, self._state_ptr(U_n), t, dt,
+                                         self._state_ptr(lam_np1, "lam_np1"), self._state_ptr(out, "lam_n")),
+                    "dg_rk_step_vjp")
+        return out
+
+    def kinetic_energy(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out
+        self._check(lib().dg_kinetic_energy(self._ctx, self._state_ptr(U), _ptr(out, 1, "J")),
+                    "dg_kinetic_energy")
+        return out
+
+    def kinetic_energy_grad(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        out = self.state_like() if out is None else out
+        self._check(lib().dg_kinetic_energy_grad(self._ctx, self._state_ptr(U), self._state_ptr(out, "lam")),
+                    "dg_kinetic_energy_grad")
+        return out
+
+    def timing_begin(self, max_launches: int):
+        self._check(lib().dg_timing_begin(self._ctx, max_launches), "dg_timing_begin")
+
+    def timing_end(self):
+        """(ms_lift, ms_rhs, n_lift, n_rhs) summed over the timed launches."""
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int * 2)()
+        self._check(lib().dg_timing_end(self._ctx, ms, cnt), "dg_timing_end")
+        return ms[0], ms[1], cnt[0], cnt[1]
+
+    def sync(self):
+        self._check(lib().dg_sync(self._ctx), "dg_sync")
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().dg_free(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solver_for(workload, *, device=None, with_adjoint=False, precision=None, viscous=True,
+               central_only=False) -> Solver:
+    """Solver for a paper_2606_18927_amd.workloads.Workload."""
+    mesh = MeshSpec(workload.N, workload.faces(), workload.bc, workload.T_wall)
+    return Solver(mesh, workload.gamma, workload.R, workload.mu, workload.Pr, viscous=viscous,
+                  precision=precision or workload.precision, central_only=central_only,
+                  with_adjoint=with_adjoint, device=device)

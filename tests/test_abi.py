@@ -1,0 +1,123 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/dgsem.h declares, and its host-only entry points (LGL tables, argument
+validation, workspace sizing) behave as documented."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2606_18927_amd import dgsem
+from oracle.basis import lgl as oracle_lgl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgsem.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(dgsem.LIB_PATH):
+        pytest.fail("libdgsem.so is not built (python -m paper_2606_18927_amd.build)")
+    return dgsem.lib()
+
+
+def test_library_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(dgsem.exported_symbols())
+
+
+def test_version(L):
+    assert dgsem.version().startswith("dgsem-gfx950")
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7, 9, 12])
+def test_host_lgl_matches_independent_oracle_basis(L, N):
+    xi, w = dgsem.lgl(N)
+    xo, wo = oracle_lgl(N)
+    assert np.allclose(xi, xo.numpy(), atol=2e-16 * 4, rtol=0)
+    assert np.allclose(w, wo.numpy(), atol=1e-15, rtol=0)
+
+
+def _desc(N=3, n=(2, 2, 2), faces=None, bc=(0, 0, 0), T_wall=1.0):
+    desc = dgsem.MeshDesc()
+    desc.N = N
+    keep = []
+    for d in range(3):
+        f = np.ascontiguousarray(faces[d] if faces else np.linspace(0, 1, n[d] + 1))
+        keep.append(f)
+        desc.nelem[d] = n[d]
+        desc.faces[d] = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        desc.bc[d] = bc[d]
+    desc.T_wall = T_wall
+    return desc, keep
+
+
+def _init(L, desc, phys):
+    ctx = ctypes.c_void_p()
+    st = L.dg_init_mesh(ctypes.byref(desc), ctypes.byref(phys), None, ctypes.byref(ctx))
+    return st, ctx
+
+
+def _phys(**kw):
+    base = dict(gamma=1.4, R=1.0, mu=0.01, Pr=0.72, viscous=1, precision=0, central_only=0)
+    base.update(kw)
+    return dgsem.Physics(base["gamma"], base["R"], base["mu"], base["Pr"], base["viscous"],
+                         base["precision"], base["central_only"])
+
+
+def test_init_mesh_validation_errors(L):
+    d, keep = _desc()
+    st, ctx = _init(L, d, _phys())
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
+    d, keep = _desc(N=4)
+    assert _init(L, d, _phys())[0] == dgsem.DG_EUNSUPPORTED
+    d, keep = _desc(faces=(np.array([0.0, 0.5, 0.4]), np.linspace(0, 1, 3), np.linspace(0, 1, 3)))
+    assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL          # non-monotone faces
+    d, keep = _desc(bc=(0, 7, 0))
+    assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL          # unknown boundary kind
+    d, keep = _desc(bc=(0, 1, 0), T_wall=0.0)
+    assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL          # wall needs T_wall > 0
+    d, keep = _desc()
+    for bad in (dict(gamma=1.0), dict(R=0.0), dict(mu=-1.0), dict(Pr=0.0), dict(precision=3)):
+        assert _init(L, d, _phys(**bad))[0] == dgsem.DG_EINVAL, bad
+    d, keep = _desc(n=(0, 2, 2))
+    assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL
+    assert L.dg_init_mesh(None, None, None, None) == dgsem.DG_EINVAL
+
+
+def test_workspace_size_and_state_errors(L):
+    d, keep = _desc(N=7, n=(3, 2, 5))
+    st, ctx = _init(L, d, _phys())
+    assert st == dgsem.DG_OK
+    n = ctypes.c_longlong()
+    assert L.dg_n_dof(ctx, ctypes.byref(n)) == dgsem.DG_OK and n.value == 30 * 512
+    fwd, adj = ctypes.c_size_t(), ctypes.c_size_t()
+    L.dg_workspace_bytes(ctx, 0, ctypes.byref(fwd))
+    L.dg_workspace_bytes(ctx, 1, ctypes.byref(adj))
+    dof = n.value
+    # three states (U ping-pong and G) plus 12 FP64 gradient components
+    assert fwd.value >= (15 + 12) * dof * 8 and fwd.value < (15 + 12) * dof * 8 + 64 * 1024
+    assert adj.value > fwd.value
+    # no workspace bound yet: device calls are refused before any HIP call
+    assert L.dg_rk_step(ctx, 0.0, 1e-3, 1) == dgsem.DG_ESTATE
+    assert L.dg_eval_rhs(ctx, None, None, 0.0) == dgsem.DG_ESTATE
+    assert b"workspace" in L.dg_last_error(ctx)
+    L.dg_free(ctx)
+    # mixed precision halves the gradient storage
+    st, ctx = _init(L, d, _phys(precision=1))
+    mixed = ctypes.c_size_t()
+    L.dg_workspace_bytes(ctx, 0, ctypes.byref(mixed))
+    assert fwd.value - mixed.value >= 12 * dof * 4 - 4096
+    L.dg_free(ctx)

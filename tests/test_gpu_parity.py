@@ -1,0 +1,265 @@
+"""Parity of the HIP operator with the FP64 CPU oracle (GPU).
+
+Criterion (FP64): per conserved variable, relative L2 error <= 1e-12 against
+the oracle on the same seeded input; gradients and kinetic energy likewise.
+Small cases compare every node (several workgroups, ragged element counts,
+walls, N = 3, 5, 7); the full N = 7, 32^3-element Taylor-Green case compares
+sampled elements, each computed by the oracle on the periodic patch of
+elements it depends on, in the launch configuration bench.py times.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import ke_grad
+from oracle.dgsem import kinetic_energy, lift, rhs, rk_step
+from oracle.mesh import Mesh
+from paper_2606_18927_amd import dgsem, workloads
+
+from _cases import random_faces, random_state
+from _gpu import (custom, grad_rel_err, need_gpu, oracle_gas, oracle_mesh, periodic_patch, rel_l2, say, state,
+                  to_dev, uniform_patch_mesh)
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _solver(mesh, g, **kw):
+    spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall)
+    return dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, **kw)
+
+
+def _lift_ref(U, mesh, g):
+    gr = lift(torch.as_tensor(U), mesh, g)
+    return torch.stack([gr[c][d] for c in range(4) for d in range(3)]).numpy()
+
+
+def _case_random(N, n, bc=("periodic",) * 3, seed=0, mu=0.01):
+    rng = np.random.default_rng(seed)
+    faces = []
+    for d in range(3):
+        if bc[d] == "wall":
+            faces.append(random_faces(n[d], -1.0, 1.0, rng))
+        else:
+            faces.append(random_faces(n[d], 0.0, 2.0 + d, rng))
+    mesh = Mesh(N, tuple(faces), bc=bc, T_wall=1.1)
+    from oracle.physics import Gas
+    g = Gas(gamma=1.4, R=1.0 / (1.4 * 0.01), mu=mu, Pr=0.72)
+    U = random_state(mesh, g.gamma, g.R, rng, vel_amp=1.0, p_mean=1.0 / (1.4 * 0.01), p_amp=0.05)
+    return mesh, g, U.numpy()
+
+
+# ------------------------------------------------------------- small cases
+
+def test_tgv_n3_lift_rhs_rk_full_parity():
+    need_gpu()
+    wl = workloads.WORKLOADS["tgv_n3_4x4x4"]
+    say("case", wl.name)
+    U, dt = state(wl)
+    mesh, g = oracle_mesh(wl), oracle_gas(wl)
+    S = dgsem.solver_for(wl)
+    Ud = to_dev(U)
+    grad = S.eval_lift(Ud).cpu().numpy().reshape(12, -1)
+    gref = _lift_ref(U, mesh, g).reshape(12, -1)
+    err = grad_rel_err(grad, gref)
+    say("lift rel L2", err)
+    assert np.all(err < TOL)
+    Ut = S.eval_rhs(Ud).cpu().numpy()
+    ref = rhs(torch.as_tensor(U), mesh, g).numpy()
+    e = rel_l2(Ut, ref)
+    say("rhs rel L2", e)
+    assert np.all(e < TOL)
+    S.set_state(Ud)
+    S.rk_step(dt, wl.nsteps)
+    S.sync()
+    Un = S.get_state().cpu().numpy()
+    Uref = rk_step(torch.as_tensor(U), mesh, g, dt, wl.nsteps).numpy()
+    e = rel_l2(Un, Uref)
+    say("rk 10 steps rel L2", e)
+    assert np.all(e < TOL)
+    # the change over the run, which is what the scheme computes, also agrees
+    dU, dref = Un.reshape(5, -1) - U.reshape(5, -1), Uref.reshape(5, -1) - U.reshape(5, -1)
+    e2 = rel_l2(dU, dref)
+    say("rk 10 steps increment rel L2", e2)
+    assert np.all(e2 < 1e-10)
+
+
+@pytest.mark.parametrize("N,n,bc", [
+    (3, (5, 3, 3), ("periodic",) * 3),                 # 45 elements: ragged last workgroup
+    (3, (1, 2, 3), ("periodic", "wall", "periodic")),  # an element that is its own x neighbour
+    (5, (3, 4, 2), ("periodic", "wall", "periodic")),
+    (5, (2, 3, 3), ("wall", "periodic", "wall")),
+    (7, (3, 2, 4), ("periodic",) * 3),
+    (7, (2, 3, 2), ("periodic", "periodic", "wall")),
+])
+def test_random_state_lift_and_rhs_parity(N, n, bc):
+    need_gpu()
+    say("case", N, n, bc)
+    mesh, g, U = _case_random(N, n, bc, seed=N * 100 + sum(n))
+    S = _solver(mesh, g)
+    Ud = to_dev(U)
+    grad = S.eval_lift(Ud).cpu().numpy().reshape(12, -1)
+    gref = _lift_ref(U, mesh, g).reshape(12, -1)
+    err = grad_rel_err(grad, gref)
+    say("lift rel L2 max", err.max())
+    assert np.all(err < TOL)
+    Ut = S.eval_rhs(Ud).cpu().numpy()
+    ref = rhs(torch.as_tensor(U), mesh, g).numpy()
+    e = rel_l2(Ut, ref)
+    say("rhs rel L2", e)
+    assert np.all(e < TOL)
+    S.sync()
+
+
+@pytest.mark.parametrize("viscous,central", [(False, False), (False, True), (True, True)])
+def test_scheme_switches_parity(viscous, central):
+    need_gpu()
+    mesh, g, U = _case_random(3, (3, 3, 2), seed=7)
+    S = _solver(mesh, g, viscous=viscous, central_only=central)
+    Ut = S.eval_rhs(to_dev(U)).cpu().numpy()
+    ref = rhs(torch.as_tensor(U), mesh, g, viscous=viscous, central_only=central).numpy()
+    e = rel_l2(Ut, ref)
+    say("switches", viscous, central, e)
+    assert np.all(e < TOL)
+
+
+def test_channel_rk_steps_parity():
+    need_gpu()
+    wl = custom("channel", 5, (3, 4, 2), seed=workloads.CHANNEL_SEED)
+    U, dt = state(wl)
+    mesh, g = oracle_mesh(wl), oracle_gas(wl)
+    S = dgsem.solver_for(wl)
+    S.set_state(to_dev(U))
+    S.rk_step(dt, 3)
+    S.sync()
+    got = S.get_state().cpu().numpy()
+    ref = rk_step(torch.as_tensor(U), mesh, g, dt, 3).numpy()
+    d = rel_l2(got.reshape(5, -1) - U.reshape(5, -1), ref.reshape(5, -1) - U.reshape(5, -1))
+    say("channel rk increment rel L2", d)
+    assert np.all(rel_l2(got, ref) < TOL)
+    assert np.all(d < 1e-10)
+
+
+def test_kinetic_energy_and_gradient():
+    need_gpu()
+    wl = custom("channel", 5, (3, 4, 2), seed=workloads.CHANNEL_SEED)
+    U, _ = state(wl)
+    mesh = oracle_mesh(wl)
+    S = dgsem.solver_for(wl)
+    Ud = to_dev(U)
+    J = S.kinetic_energy(Ud).item()
+    Jref = kinetic_energy(torch.as_tensor(U), mesh).item()
+    assert abs(J - Jref) < 1e-13 * abs(Jref)
+    lam = S.kinetic_energy_grad(Ud).cpu().numpy()
+    lref = ke_grad(torch.as_tensor(U), mesh).numpy()
+    assert np.allclose(lam.reshape(5, -1), lref.reshape(5, -1), rtol=1e-13, atol=1e-300)
+
+
+def test_free_stream_and_determinism():
+    need_gpu()
+    wl = custom("freestream", 7, (3, 2, 2))
+    U, _ = state(wl)
+    S = dgsem.solver_for(wl)
+    Ud = to_dev(U)
+    a = S.eval_rhs(Ud)
+    b = S.eval_rhs(Ud)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    scale = (U[4].max() + wl.R) * (2.0 / (2 * np.pi / 3))
+    assert a.abs().max().item() < 1e-13 * scale
+
+
+def test_nonphysical_state_is_reported():
+    need_gpu()
+    mesh, g, U = _case_random(3, (2, 2, 2), seed=3)
+    U = U.copy()
+    U[0, 0, 0, 0, 1, 1, 1] = -1.0
+    S = _solver(mesh, g)
+    S.eval_rhs(to_dev(U))
+    with pytest.raises(dgsem.DgsemError) as ei:
+        S.sync()
+    assert ei.value.status == dgsem.DG_ENONPHYS
+    S.sync()  # the status word was cleared
+
+
+# --------------------------------------------------- full N=7, 32^3 workload
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = workloads.WORKLOADS["tgv_n7_32x32x32"]
+    say("building", wl.name)
+    U, dt = state(wl)
+    S = dgsem.solver_for(wl)
+    return wl, U, dt, S
+
+
+SAMPLES = [(0, 0, 0), (31, 17, 5), (13, 31, 30), (7, 8, 16)]
+
+
+def test_full_size_eval_rhs_sampled(big):
+    wl, U, dt, S = big
+    Ut = S.eval_rhs(to_dev(U)).cpu().numpy().reshape(U.shape)
+    S.sync()
+    h = [2 * np.pi / 32] * 3
+    pm = uniform_patch_mesh(wl.N, h, 1, wl)
+    g = oracle_gas(wl)
+    for c in SAMPLES:
+        say("sample", c)
+        P = periodic_patch(U, c, 1)
+        ref = rhs(torch.as_tensor(np.ascontiguousarray(P)), pm, g).numpy()[:, 1, 1, 1]
+        got = Ut[:, c[2], c[1], c[0]]
+        e = rel_l2(got, ref)
+        say("  rel L2", e)
+        assert np.all(e < TOL)
+
+
+def test_full_size_rk_step_sampled(big):
+    """One RK step (5 stages): each stage widens the dependence by one element,
+    so the centre of an 11^3 periodic patch is exact after the step."""
+    wl, U, dt, S = big
+    S.set_state(to_dev(U))
+    S.rk_step(dt, 1)
+    S.sync()
+    got_all = S.get_state().cpu().numpy().reshape(U.shape)
+    h = [2 * np.pi / 32] * 3
+    r = 5
+    pm = uniform_patch_mesh(wl.N, h, r, wl)
+    g = oracle_gas(wl)
+    for c in SAMPLES[1:2]:
+        say("rk sample", c)
+        P = periodic_patch(U, c, r)
+        ref = rk_step(torch.as_tensor(np.ascontiguousarray(P)), pm, g, dt, 1).numpy()[:, r, r, r]
+        got = got_all[:, c[2], c[1], c[0]]
+        U0 = U[:, c[2], c[1], c[0]]
+        e = rel_l2(got, ref)
+        e2 = rel_l2(got - U0, ref - U0)
+        say("  rel L2", e, "increment", e2)
+        assert np.all(e < TOL)
+        assert np.all(e2 < 1e-10)
+
+
+def test_full_size_conservation_over_run(big):
+    """Over the full 100-step run the discrete integrals of all five conserved
+    variables stay constant (periodic box), and run-to-run results are bitwise equal."""
+    wl, U, dt, S = big
+    mesh = oracle_mesh(wl)
+    wq = mesh.quadrature_weights().numpy()
+    S.set_state(to_dev(U))
+    S.rk_step(dt, wl.nsteps)
+    S.sync()
+    A = S.get_state()
+    S.set_state(to_dev(U))
+    S.rk_step(dt, wl.nsteps)
+    S.sync()
+    B = S.get_state()
+    assert torch.equal(A, B)
+    Un = A.cpu().numpy().reshape(U.shape)
+    for v in range(5):
+        i0 = (wq * U[v]).sum()
+        i1 = (wq * Un[v]).sum()
+        scale = (wq * np.abs(U[v])).sum()
+        say("integral", v, i0, i1)
+        assert abs(i1 - i0) < 1e-12 * scale
