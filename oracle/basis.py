@@ -9,12 +9,18 @@ definitions:
   polynomial of degree N);
 * weights: w_i = 2 / (N (N+1) P_N(xi_i)^2);
 * derivative matrix: D_im = l_m'(xi_i) for the Lagrange polynomials l_m of the
-  nodes, written in the classical closed form for LGL points
-      D_im = P_N(xi_i) / (P_N(xi_m) (xi_i - xi_m))     (i != m)
-      D_00 = -N(N+1)/4,  D_NN = +N(N+1)/4,  D_ii = 0 otherwise.
+  nodes; the off-diagonal entries are written in the classical closed form for
+  LGL points
+      D_im = P_N(xi_i) / (P_N(xi_m) (xi_i - xi_m))     (i != m),
+  and the diagonal by the negative-sum rule D_ii = -sum_{m != i} D_im.
+  Reading: the exact D annihilates constants (its diagonal is -N(N+1)/4,
+  0, ..., 0, +N(N+1)/4); the negative-sum diagonal keeps that property in
+  floating point, which fixes the discrete operator to rounding on nearly
+  constant data (low-Mach pressure), where rounded closed-form diagonals leave
+  row sums of a few ulps that dominate the result.
 
-This deliberately differs in method from any barycentric/Newton construction so
-that an independent implementation is pinned against it up to rounding.
+The off-diagonal construction differs in method from any barycentric/Newton
+construction so that an independent implementation is pinned against it.
 """
 
 from __future__ import annotations
@@ -51,7 +57,7 @@ def lgl(N: int):
 
 
 def diff_matrix(N: int) -> torch.Tensor:
-    """LGL nodal derivative matrix D[i, m] = l_m'(xi_i) (closed form, see module doc)."""
+    """LGL nodal derivative matrix D[i, m] = l_m'(xi_i) (see module doc)."""
     x, _ = lgl(N)
     x = x.numpy()
     PN = npleg.legval(x, _legendre_coeffs(N))
@@ -60,8 +66,8 @@ def diff_matrix(N: int) -> torch.Tensor:
         for m in range(N + 1):
             if i != m:
                 D[i, m] = PN[i] / (PN[m] * (x[i] - x[m]))
-    D[0, 0] = -N * (N + 1) / 4.0
-    D[N, N] = N * (N + 1) / 4.0
+    for i in range(N + 1):
+        D[i, i] = -sum(D[i, m] for m in range(N + 1) if m != i)
     return torch.tensor(D, dtype=torch.float64)
 
 

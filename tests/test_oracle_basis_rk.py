@@ -97,6 +97,16 @@ def test_D_summation_by_parts(N):
     assert torch.allclose(Q + Q.T, B, atol=1e-14, rtol=0)
 
 
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7])
+def test_D_diagonal_matches_closed_form(N):
+    """The negative-sum diagonal equals the exact diagonal -N(N+1)/4, 0, ..., 0, N(N+1)/4."""
+    d = torch.diagonal(diff_matrix(N))
+    want = torch.zeros(N + 1, dtype=torch.float64)
+    want[0], want[N] = -N * (N + 1) / 4.0, N * (N + 1) / 4.0
+    assert torch.allclose(d, want, atol=1e-13 * N * N, rtol=0)
+    assert (diff_matrix(N).sum(1)).abs().max() < 4e-16 * N * N
+
+
 def test_lagrange_cardinal():
     x, _ = lgl(5)
     assert torch.allclose(lagrange_eval(5, x.numpy()), torch.eye(6, dtype=torch.float64), atol=1e-14)
