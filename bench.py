@@ -3,7 +3,7 @@
 Workload: Taylor-Green vortex at N = 7 on 32^3 periodic elements (16.8 M DOF,
 DOF = one LGL node), 1 % seeded velocity noise, FP64, the five-stage
 low-storage RK at CFL 0.5.  One "step" is one RK step: five stages, each a
-lifting kernel and a fused right-hand-side + RK-update kernel.
+face viscous-flux kernel and a fused lifting + right-hand-side + RK-update kernel.
 
 Prints one JSON line.  `value` is ns per DOF per RK stage (FP64), i.e. the
 paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
@@ -29,13 +29,15 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 METRIC = "ns per DOF per RK stage (FP64 vs mixed) at N=7; adjoint/forward time ratio"
 
-# algorithmic HBM bytes per DOF (8 B per FP64 value, 4 B per FP32 gradient)
-#   lift:       read U (5) + write grad (12)
-#   rhs+RK:     read U (5) + grad (12) + G (5, not on stage 1) + write G (5) + U' (5)
-BYTES = {
-    "fp64": {"lift": 40 + 96, "rk": 40 + 96 + 40 + 40 + 40, "rk_first": 40 + 96 + 40 + 40},
-    "mixed": {"lift": 40 + 48, "rk": 40 + 48 + 40 + 40 + 40, "rk_first": 40 + 48 + 40 + 40},
-}
+# Algorithmic HBM bytes per DOF and launch (N = 7: 3 face-flux values per DOF,
+# 6 faces x 4 components x 64 face nodes / 512 nodes; 8 B FP64, 4 B FP32):
+#   face flux kernel: read U (5) + write the face viscous fluxes (3)
+#   fused RHS + RK:   read U (5) + the neighbours' face fluxes (3) + G (5, not on
+#                     the first stage, A_1 = 0) + write G (5) + U' (5)
+def alg_bytes(precision: str, N: int = 7):
+    r = 8 if precision == "fp64" else 4
+    ff = 24.0 / (N + 1) * r
+    return {"face": 40 + ff, "rk": 40 + ff + 40 + 40 + 40, "rk_first": 40 + ff + 40 + 40}
 
 
 def _parse():
@@ -130,16 +132,17 @@ def run_precision(wl, U, dt, precision, steps, warmup):
     dof = S.n_dof
     stages = steps * 5
     ns = ms * 1e6 / (dof * stages)
-    b = BYTES[precision]
+    b = alg_bytes(precision, wl.N)
     rk_bytes = dof * (b["rk"] * (stages - steps) + b["rk_first"] * steps) / stages
     rk_avg_s = rk_ms / 1e3 / n_rk
     lift_avg_s = lift_ms / 1e3 / max(n_lift, 1)
     res = {
         "ns_per_dof_stage": ns, "ms_per_step": ms / steps, "dof": dof,
-        "rk_kernel_ms": rk_ms / n_rk, "lift_kernel_ms": lift_ms / max(n_lift, 1),
+        "rk_kernel_ms": rk_ms / n_rk, "face_kernel_ms": lift_ms / max(n_lift, 1),
         "rk_kernel_gbs": rk_bytes / rk_avg_s / 1e9,
-        "lift_kernel_gbs": dof * b["lift"] / lift_avg_s / 1e9,
-        "step_alg_gbs": dof * (b["lift"] * stages + b["rk"] * (stages - steps) + b["rk_first"] * steps)
+        "face_kernel_gbs": dof * b["face"] / lift_avg_s / 1e9,
+        "step_alg_bytes_per_dof": b["face"] + (b["rk"] * (stages - steps) + b["rk_first"] * steps) / stages,
+        "step_alg_gbs": dof * (b["face"] * stages + b["rk"] * (stages - steps) + b["rk_first"] * steps)
         / (ms / 1e3) / 1e9,
         "rk_bytes_per_launch": rk_bytes,
     }
@@ -206,7 +209,9 @@ def main():
             "traffic": None,
             "kernel_ms": fp64["rk_kernel_ms"],
             "bytes_per_launch": fp64["rk_bytes_per_launch"],
-            "lift_kernel_gbs": fp64["lift_kernel_gbs"],
+            "face_kernel_gbs": fp64["face_kernel_gbs"],
+            "face_kernel_ms": fp64["face_kernel_ms"],
+            "step_alg_bytes_per_dof": fp64["step_alg_bytes_per_dof"],
             "step_alg_gbs": fp64["step_alg_gbs"],
             "step_frac": fp64["step_alg_gbs"] / HBM_PEAK_GBS,
             "triad_gbs": triad,

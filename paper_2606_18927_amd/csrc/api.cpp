@@ -41,7 +41,7 @@ dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 struct Layout {
-  size_t D, w, s[3], status, partial, U0, U1, G, grad;
+  size_t D, w, s[3], status, partial, U0, U1, G, ffv;
   size_t stages, lamG, lamU, ubar, gbar, tmp;
   size_t fwd_end, adj_end;
 };
@@ -51,7 +51,8 @@ Layout layout(const dg_ctx* c) {
   const size_t NP = c->N + 1;
   const size_t dof = static_cast<size_t>(c->n_dof);
   const size_t state = 5 * dof * sizeof(double);
-  const size_t gbytes = 12 * dof * (c->phys.precision == DG_MIXED ? sizeof(float) : sizeof(double));
+  const size_t rsize = c->phys.precision == DG_MIXED ? sizeof(float) : sizeof(double);
+  const size_t fbytes = static_cast<size_t>(c->nE) * dg::face_flux_values_per_element(c->N) * rsize;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
@@ -66,7 +67,7 @@ Layout layout(const dg_ctx* c) {
   L.U0 = take(state);
   L.U1 = take(state);
   L.G = take(state);
-  L.grad = c->phys.viscous ? take(gbytes) : off;
+  L.ffv = c->phys.viscous ? take(fbytes) : off;
   L.fwd_end = off;
   L.stages = take(5 * state);
   L.lamG = take(state);
@@ -137,12 +138,12 @@ dg_status eval_rhs_into(dg_ctx* c, const double* U, double* Ut) {
   const dg::DevPhys p = dev_phys(c);
   const dg::DevBasis b = dev_basis(c);
   if (c->phys.viscous) {
-    dg_status st = hip_check(c, dg::launch_lift(c->N, c->phys.precision, m, p, b, U, c->grad, c->stream),
-                             "lift kernel");
+    dg_status st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, U, c->ffv, c->stream),
+                             "face flux kernel");
     if (st != DG_OK) return st;
     mark(c, 0);
   }
-  dg_status st = hip_check(c, dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->grad, Ut, c->dstatus,
+  dg_status st = hip_check(c, dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->ffv, Ut, c->dstatus,
                                              c->stream),
                            "rhs kernel");
   if (st == DG_OK) mark(c, 1);
@@ -247,7 +248,7 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
   c->U[1] = reinterpret_cast<double*>(ws + L.U1);
   c->cur = 0;
   c->G = reinterpret_cast<double*>(ws + L.G);
-  c->grad = c->phys.viscous ? static_cast<void*>(ws + L.grad) : nullptr;
+  c->ffv = c->phys.viscous ? static_cast<void*>(ws + L.ffv) : nullptr;
   if (with_adjoint) {
     c->stages = reinterpret_cast<double*>(ws + L.stages);
     c->lamG = reinterpret_cast<double*>(ws + L.lamG);
@@ -317,8 +318,7 @@ dg_status dg_eval_lift(dg_ctx* c, const double* U, double* grad) {
   if (st != DG_OK) return st;
   if (!U || !grad) return fail(c, DG_EINVAL, "bad pointers");
   if (c->phys.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "eval_lift: FP64 contexts only");
-  return hip_check(c, dg::launch_lift(c->N, DG_FP64, dev_mesh(c), dev_phys(c), dev_basis(c), U, grad,
-                                      c->stream),
+  return hip_check(c, dg::launch_lift(c->N, dev_mesh(c), dev_phys(c), dev_basis(c), U, grad, c->stream),
                    "lift kernel");
 }
 
@@ -334,13 +334,13 @@ dg_status dg_rk_step(dg_ctx* c, double /*t*/, double dt, int nsteps) {
       const double* Uin = c->U[c->cur];
       double* Uout = c->U[c->cur ^ 1];
       if (c->phys.viscous) {
-        if ((st = hip_check(c, dg::launch_lift(c->N, c->phys.precision, m, p, b, Uin, c->grad, c->stream),
-                            "lift kernel")) != DG_OK)
+        if ((st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, Uin, c->ffv, c->stream),
+                            "face flux kernel")) != DG_OK)
           return st;
         mark(c, 0);
       }
       const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
-      if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, Uin, c->grad, c->G,
+      if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, Uin, c->ffv, c->G,
                                                  Uout, stage, c->dstatus, c->stream),
                           "rk stage kernel")) != DG_OK)
         return st;

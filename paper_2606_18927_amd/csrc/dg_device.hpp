@@ -1,0 +1,168 @@
+// Device helpers shared by the forward, lifting and adjoint kernels.
+#pragma once
+
+#include "dg_internal.hpp"
+
+namespace dg {
+
+// Workgroup shape per polynomial degree: EPB whole elements per workgroup,
+// BS lanes, one lane per node and (in the face phases) one lane per face node:
+// BS >= EPB (N+1)^3 and BS >= EPB 6 (N+1)^2.
+template <int N>
+struct Cfg;
+template <>
+struct Cfg<3> {
+  static constexpr int EPB = 2, BS = 192;
+};
+template <>
+struct Cfg<5> {
+  static constexpr int EPB = 1, BS = 256;
+};
+template <>
+struct Cfg<7> {
+  static constexpr int EPB = 1, BS = 512;
+};
+
+template <int N>
+struct Geo {
+  static constexpr int NP = N + 1, NF = NP * NP, NN = NF * NP;
+  static constexpr int RS = NP + 1;        // padded x-row stride of an LDS block
+  static constexpr int EB = RS * NP * NP;  // LDS entries per element and field
+  __device__ static constexpr int lds(int i, int j, int k) { return i + RS * (j + NP * k); }
+};
+
+template <int N>
+__host__ __device__ constexpr int n_face_tasks() {
+  return Cfg<N>::EPB * 6 * (N + 1) * (N + 1);
+}
+
+// Workgroup b of nb -> element block, so that XCD x = b % 8 (each XCD has its
+// own L2) covers one contiguous range of element blocks.  Bijective for any nb.
+__device__ inline int xcd_remap(int b, int nb) {
+  constexpr int X = 8;
+  const int q = nb / X, r = nb % X;
+  const int x = b % X, l = b / X;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
+__device__ inline void elem_coords(long long e, const DevMesh& m, int& ex, int& ey, int& ez) {
+  ex = static_cast<int>(e % m.n[0]);
+  const long long t = e / m.n[0];
+  ey = static_cast<int>(t % m.n[1]);
+  ez = static_cast<int>(t / m.n[1]);
+}
+
+// Face neighbour of element (ex, ey, ez) across its lower (up = false) or
+// upper face normal to d; -1 on a wall.
+__device__ inline long long neighbour(const DevMesh& m, int ex, int ey, int ez, int d, bool up) {
+  int c[3] = {ex, ey, ez};
+  int v = c[d] + (up ? 1 : -1);
+  if (v < 0 || v >= m.n[d]) {
+    if (m.bc[d] != DG_BC_PERIODIC) return -1;
+    v = (v + m.n[d]) % m.n[d];
+  }
+  c[d] = v;
+  return c[0] + static_cast<long long>(m.n[0]) * (c[1] + static_cast<long long>(m.n[1]) * c[2]);
+}
+
+// Node (i, j, k) of face f = 2 d + up with in-face coordinates (a, b):
+// d = 0: (i, j, k) = (n, a, b); d = 1: (a, n, b); d = 2: (a, b, n), n = 0 or N.
+template <int N>
+__device__ inline void face_node(int d, bool up, int a, int b, int& i, int& j, int& k) {
+  const int n = up ? N : 0;
+  i = d == 0 ? n : a;
+  j = d == 0 ? a : (d == 1 ? n : b);
+  k = d == 2 ? n : b;
+}
+
+// Decoded face task t of a workgroup.
+template <int N>
+struct FaceTask {
+  int le, f, d, ab, oi, oj, ok;
+  bool up;
+  __device__ FaceTask(int t) {
+    constexpr int NF = (N + 1) * (N + 1);
+    le = t / (6 * NF);
+    const int rr = t - le * 6 * NF;
+    f = rr / NF;
+    ab = rr - f * NF;
+    d = f >> 1;
+    up = (f & 1) != 0;
+    face_node<N>(d, up, ab % (N + 1), ab / (N + 1), oi, oj, ok);
+  }
+  // node of the neighbour element that coincides with the own face node
+  __device__ int nb_node() const {
+    const int opp = up ? 0 : N;
+    const int ni = d == 0 ? opp : oi, nj = d == 1 ? opp : oj, nk = d == 2 ? opp : ok;
+    return ni + (N + 1) * (nj + (N + 1) * nk);
+  }
+  __device__ int own_node() const { return oi + (N + 1) * (oj + (N + 1) * ok); }
+};
+
+struct Prim {
+  double rho, u, v, w, p, e, T;
+};
+
+// Ideal-gas primitive recovery, always FP64.
+__device__ inline Prim primitives(const double s[5], const DevPhys& ph) {
+  Prim P;
+  const double r = s[0];
+  const double ir = 1.0 / r;
+  P.rho = r;
+  P.u = s[1] * ir;
+  P.v = s[2] * ir;
+  P.w = s[3] * ir;
+  P.p = ph.gm1 * (s[4] - 0.5 * r * (P.u * P.u + P.v * P.v + P.w * P.w));
+  P.e = s[4] * ir;
+  P.T = P.p * ph.inv_R * ir;
+  return P;
+}
+
+__device__ inline double vel(const Prim& P, int d) { return d == 0 ? P.u : (d == 1 ? P.v : P.w); }
+
+__device__ inline void load_state(const double* U, long long stride, long long idx, double u[5]) {
+#pragma unroll
+  for (int v = 0; v < 5; ++v) u[v] = U[v * stride + idx];
+}
+
+// Kennedy-Gruber two-point flux along d of states a, b = (rho, u, v, w, p, e).
+template <int d, typename R>
+__device__ inline void kg_flux(const R a[6], const R b[6], R f[5]) {
+  const R h = R(0.5);
+  const R rho = h * (a[0] + b[0]);
+  const R ud = h * (a[1 + d] + b[1 + d]);
+  const R p = h * (a[4] + b[4]);
+  const R e = h * (a[5] + b[5]);
+  const R mass = rho * ud;
+  f[0] = mass;
+  f[1] = mass * (h * (a[1] + b[1]));
+  f[2] = mass * (h * (a[2] + b[2]));
+  f[3] = mass * (h * (a[3] + b[3]));
+  f[1 + d] += p;
+  f[4] = mass * e + p * ud;
+}
+
+// Viscous flux along d: g[3 q + b] = d q / d x_b for q in (u, v, w, T);
+// returns (tau_1d, tau_2d, tau_3d, u_a tau_ad + kappa dT/dx_d).
+template <int d, typename R>
+__device__ inline void viscous_flux(R u, R v, R w, const R g[12], R mu, R kappa, R f[4]) {
+  const R div = g[0] + g[4] + g[8];
+  R t0 = mu * (g[0 * 3 + d] + g[d * 3 + 0]);
+  R t1 = mu * (g[1 * 3 + d] + g[d * 3 + 1]);
+  R t2 = mu * (g[2 * 3 + d] + g[d * 3 + 2]);
+  const R dd = R(2.0 / 3.0) * mu * div;
+  if (d == 0) t0 -= dd;
+  if (d == 1) t1 -= dd;
+  if (d == 2) t2 -= dd;
+  f[0] = t0;
+  f[1] = t1;
+  f[2] = t2;
+  f[3] = u * t0 + v * t1 + w * t2 + kappa * g[9 + d];
+}
+
+template <int N>
+inline int n_blocks(long long nE) {
+  return static_cast<int>((nE + Cfg<N>::EPB - 1) / Cfg<N>::EPB);
+}
+
+}  // namespace dg

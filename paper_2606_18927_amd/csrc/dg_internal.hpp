@@ -42,16 +42,20 @@ struct Stage {
   int read_G;         // 0 on the first stage (A_1 = 0): G is not read
 };
 
-// Kernel launchers (fwd_kernels.hip).  grad is double* for DG_FP64 and
-// float* for DG_MIXED.
-hipError_t launch_lift(int N, int precision, const DevMesh& m, const DevPhys& p,
-                       const DevBasis& b, const double* U, void* grad, hipStream_t s);
+// Kernel launchers.  ffv (face viscous fluxes, face_flux_values_per_element
+// values per element) is double* for DG_FP64 and float* for DG_MIXED.
+size_t face_flux_values_per_element(int N);
+hipError_t launch_face_flux(int N, int precision, const DevMesh& m, const DevPhys& p,
+                            const DevBasis& b, const double* U, void* ffv, hipStream_t s);
 hipError_t launch_rhs(int N, int precision, const DevMesh& m, const DevPhys& p,
-                      const DevBasis& b, const double* U, const void* grad, double* Ut,
+                      const DevBasis& b, const double* U, const void* ffv, double* Ut,
                       int* status, hipStream_t s);
 hipError_t launch_rk_stage(int N, int precision, const DevMesh& m, const DevPhys& p,
-                           const DevBasis& b, const double* U, const void* grad, double* G,
+                           const DevBasis& b, const double* U, const void* ffv, double* G,
                            double* U_out, const Stage& st, int* status, hipStream_t s);
+// Stand-alone FP64 lifting, grad[3 q + d][e][node] (lift_kernels.hip).
+hipError_t launch_lift(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                       const double* U, double* grad, hipStream_t s);
 
 // Reductions and elementwise kernels (aux_kernels.hip).
 hipError_t launch_kinetic_energy(int N, const DevMesh& m, const double* w, const double* U,
@@ -94,7 +98,7 @@ struct dg_ctx {
   double* U[2] = {nullptr, nullptr};
   int cur = 0;
   double* G = nullptr;
-  void* grad = nullptr;
+  void* ffv = nullptr;        // face viscous fluxes of the current stage
   // adjoint buffers
   double* stages = nullptr;   // 5 stage input states of one step
   double* lamG = nullptr;

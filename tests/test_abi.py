@@ -107,17 +107,18 @@ def test_workspace_size_and_state_errors(L):
     L.dg_workspace_bytes(ctx, 0, ctypes.byref(fwd))
     L.dg_workspace_bytes(ctx, 1, ctypes.byref(adj))
     dof = n.value
-    # three states (U ping-pong and G) plus 12 FP64 gradient components
-    assert fwd.value >= (15 + 12) * dof * 8 and fwd.value < (15 + 12) * dof * 8 + 64 * 1024
+    # three states (U ping-pong and G) plus the face viscous fluxes
+    # (6 faces x 4 components x 64 face nodes per 512-node element = 3 per DOF)
+    assert fwd.value >= (15 + 3) * dof * 8 and fwd.value < (15 + 3) * dof * 8 + 64 * 1024
     assert adj.value > fwd.value
     # no workspace bound yet: device calls are refused before any HIP call
     assert L.dg_rk_step(ctx, 0.0, 1e-3, 1) == dgsem.DG_ESTATE
     assert L.dg_eval_rhs(ctx, None, None, 0.0) == dgsem.DG_ESTATE
     assert b"workspace" in L.dg_last_error(ctx)
     L.dg_free(ctx)
-    # mixed precision halves the gradient storage
+    # mixed precision halves the face-flux storage
     st, ctx = _init(L, d, _phys(precision=1))
     mixed = ctypes.c_size_t()
     L.dg_workspace_bytes(ctx, 0, ctypes.byref(mixed))
-    assert fwd.value - mixed.value >= 12 * dof * 4 - 4096
+    assert fwd.value - mixed.value >= 3 * dof * 4 - 4096
     L.dg_free(ctx)
