@@ -28,6 +28,7 @@ struct Geo {
   static constexpr int NP = N + 1, NF = NP * NP, NN = NF * NP;
   static constexpr int RS = NP + 1;        // padded x-row stride of an LDS block
   static constexpr int EB = RS * NP * NP;  // LDS entries per element and field
+  static constexpr int DS = NP + 1;        // padded row stride of D in LDS
   __device__ static constexpr int lds(int i, int j, int k) { return i + RS * (j + NP * k); }
 };
 
@@ -45,11 +46,15 @@ __device__ inline int xcd_remap(int b, int nb) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
 }
 
+// Element counts are below 2^31 (the host validates nE <= 2^28), so element
+// indices and their (ex, ey, ez) decomposition use 32-bit unsigned arithmetic.
 __device__ inline void elem_coords(long long e, const DevMesh& m, int& ex, int& ey, int& ez) {
-  ex = static_cast<int>(e % m.n[0]);
-  const long long t = e / m.n[0];
-  ey = static_cast<int>(t % m.n[1]);
-  ez = static_cast<int>(t / m.n[1]);
+  const unsigned ue = static_cast<unsigned>(e);
+  const unsigned nx = static_cast<unsigned>(m.n[0]), ny = static_cast<unsigned>(m.n[1]);
+  const unsigned t = ue / nx;
+  ex = static_cast<int>(ue - t * nx);
+  ez = static_cast<int>(t / ny);
+  ey = static_cast<int>(t - static_cast<unsigned>(ez) * ny);
 }
 
 // Face neighbour of element (ex, ey, ez) across its lower (up = false) or
@@ -59,10 +64,10 @@ __device__ inline long long neighbour(const DevMesh& m, int ex, int ey, int ez, 
   int v = c[d] + (up ? 1 : -1);
   if (v < 0 || v >= m.n[d]) {
     if (m.bc[d] != DG_BC_PERIODIC) return -1;
-    v = (v + m.n[d]) % m.n[d];
+    v = v < 0 ? m.n[d] - 1 : 0;
   }
   c[d] = v;
-  return c[0] + static_cast<long long>(m.n[0]) * (c[1] + static_cast<long long>(m.n[1]) * c[2]);
+  return static_cast<long long>(c[0] + m.n[0] * (c[1] + m.n[1] * c[2]));
 }
 
 // Node (i, j, k) of face f = 2 d + up with in-face coordinates (a, b):

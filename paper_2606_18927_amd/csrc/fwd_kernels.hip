@@ -50,9 +50,9 @@ __device__ inline void line_sums(const R* sD, const R* q, int i, int j, int k, R
   ax = ay = az = R(0);
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    ax += sD[i * NP + m] * q[Gm::lds(m, j, k)];
-    ay += sD[j * NP + m] * q[Gm::lds(i, m, k)];
-    az += sD[k * NP + m] * q[Gm::lds(i, j, m)];
+    ax += sD[i * Gm::DS + m] * q[Gm::lds(m, j, k)];
+    ay += sD[j * Gm::DS + m] * q[Gm::lds(i, m, k)];
+    az += sD[k * Gm::DS + m] * q[Gm::lds(i, j, m)];
   }
 }
 
@@ -145,14 +145,46 @@ __device__ inline void element_ref(const double* U, long long stride, long long 
 // --------------------------------------------------------------------------
 // k_face_flux: f_v,d on the face planes, layout ffv[e][face][c][ab]
 // --------------------------------------------------------------------------
+// Face node number t (0 <= t < n_face_nodes) of an element -> (i, j, k): the
+// two k planes first, then the boundary ring of each interior k plane.
+template <int N>
+__device__ inline void face_node_of(int t, int& i, int& j, int& k) {
+  constexpr int NP = N + 1, NF = NP * NP, RING = 4 * N;
+  if (t < 2 * NF) {
+    k = t < NF ? 0 : N;
+    const int ab = t < NF ? t : t - NF;
+    i = ab % NP;
+    j = ab / NP;
+    return;
+  }
+  const int r = t - 2 * NF;
+  k = 1 + r / RING;
+  const int q = r % RING;
+  if (q < NP) {
+    i = q; j = 0;
+  } else if (q < 2 * NP) {
+    i = q - NP; j = N;
+  } else if (q < 2 * NP + N - 1) {
+    i = 0; j = q - 2 * NP + 1;
+  } else {
+    i = N; j = q - (2 * NP + N - 1) + 1;
+  }
+}
+
+template <int N>
+__host__ __device__ constexpr int n_face_nodes() {
+  return 2 * (N + 1) * (N + 1) + (N - 1) * 4 * N;
+}
+
 template <int N, typename R>
-__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_face_flux(const double* __restrict__ U,
-                                                           R* __restrict__ ffv, DevMesh mesh,
-                                                           DevPhys ph, DevBasis basis) {
+__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_face_flux(
+    const double* __restrict__ U, R* __restrict__ ffv, DevMesh mesh, DevPhys ph, DevBasis basis) {
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB;
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
-  __shared__ R sD[NP * NP];
+  constexpr int NFN = n_face_nodes<N>();
+  static_assert(EPB * NFN <= BS, "one lane per face node");
+  __shared__ R sD[NP * Gm::DS];
   __shared__ R sq[EPB][4][EB];
   __shared__ R ssq[EPB][6][4][NF];
 
@@ -160,60 +192,65 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   const long long nE = mesh.nE;
   const long long stride = nE * NN;
   const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
-  for (int t = tid; t < NP * NP; t += BS) sD[t] = static_cast<R>(basis.D[t]);
+  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * Gm::DS + t % NP] = static_cast<R>(basis.D[t]);
+  int ex0 = 0, ey0 = 0, ez0 = 0;
+  elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
 
-  const int le = tid / NN;
-  const int node = tid - le * NN;
-  const long long e = e0 + le;
-  const bool active = le < EPB && e < nE;
-  const int i = node % NP, j = (node / NP) % NP, k = node / NF;
-
+  // P1: face lanes form the BR1 lifting corrections (FP64), node lanes stage
+  // (u, v, w, T - T_ref) in LDS
   if (tid < n_face_tasks<N>()) {
     const FaceTask<N> ft(tid);
-    const long long te = e0 + ft.le;
+    const long long te = EPB == 1 ? e0 : e0 + ft.le;
     if (te < nE) {
-      int ex, ey, ez;
-      elem_coords(te, mesh, ex, ey, ez);
+      int ex = ex0, ey = ey0, ez = ez0;
+      if (EPB > 1) elem_coords(te, mesh, ex, ey, ez);
       const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
-      double so[5];
+      double so[5], sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
       load_state(U, stride, te * NN + ft.own_node(), so);
-      const Prim Po = primitives(so, ph);
-      double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
       if (nb >= 0) load_state(U, stride, nb * NN + ft.nb_node(), sn);
-      const Prim Pn = primitives(sn, ph);
       double corr[4];
-      lifting_correction(Po, Pn, nb < 0, mesh.T_wall, ft.up, basis.inv_w_end, corr);
+      lifting_correction(primitives(so, ph), primitives(sn, ph), nb < 0, mesh.T_wall, ft.up,
+                         basis.inv_w_end, corr);
 #pragma unroll
       for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
     }
   }
-  const bool on_face = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
-  R u = R(0), v = R(0), w = R(0);
-  if (active) {
-    double s[5];
-    load_state(U, stride, e * NN + node, s);
-    const Prim P = primitives(s, ph);
-    double p_ref, e_ref, T_ref;
-    element_ref<R>(U, stride, e, NN, ph, p_ref, e_ref, T_ref);
-    const int l = Gm::lds(i, j, k);
-    u = static_cast<R>(P.u);
-    v = static_cast<R>(P.v);
-    w = static_cast<R>(P.w);
-    sq[le][0][l] = u;
-    sq[le][1][l] = v;
-    sq[le][2][l] = w;
-    sq[le][3][l] = static_cast<R>(P.T - T_ref);
+  {
+    const int le = EPB == 1 ? 0 : tid / NN;
+    const int node = tid - le * NN;
+    const long long e = EPB == 1 ? e0 : e0 + le;
+    if ((EPB == 1 ? tid < NN : le < EPB) && e < nE) {
+      const int i = node % NP, j = (node / NP) % NP, k = node / NF;
+      double s[5];
+      load_state(U, stride, e * NN + node, s);
+      const Prim P = primitives(s, ph);
+      double p_ref, e_ref, T_ref;
+      element_ref<R>(U, stride, e, NN, ph, p_ref, e_ref, T_ref);
+      const int l = Gm::lds(i, j, k);
+      sq[le][0][l] = static_cast<R>(P.u);
+      sq[le][1][l] = static_cast<R>(P.v);
+      sq[le][2][l] = static_cast<R>(P.w);
+      sq[le][3][l] = static_cast<R>(P.T - T_ref);
+    }
   }
   __syncthreads();
 
-  if (active && on_face) {
-    int ex, ey, ez;
-    elem_coords(e, mesh, ex, ey, ez);
+  // P2: one lane per face node: lifted gradients and f_v,d of each face the
+  // node lies on
+  const int le = EPB == 1 ? 0 : tid / NFN;
+  const long long e = EPB == 1 ? e0 : e0 + le;
+  if ((EPB == 1 ? tid < NFN : le < EPB) && e < nE) {
+    int i, j, k;
+    face_node_of<N>(tid - le * NFN, i, j, k);
+    int ex = ex0, ey = ey0, ez = ez0;
+    if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
     R g[12];
     lifted_gradients<N, R>(sD, sq[le][0], sq[le][1], sq[le][2], sq[le][3], ssq[le], i, j, k,
                            static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
                            static_cast<R>(mesh.s[2][ez]), g);
     const R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
+    const int l = Gm::lds(i, j, k);
+    const R u = sq[le][0][l], v = sq[le][1][l], w = sq[le][2][l];
     R* out = ffv + e * (6 * 4 * NF);
     R f[4];
     if (i == 0 || i == N) {
@@ -258,7 +295,7 @@ __device__ inline void volume_sweep(const R (&own)[6], int i, int j, int k, cons
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
     const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
-    const R Dim = sD[idx * NP + m];
+    const R Dim = sD[idx * Gm::DS + m];
     R b[6];
 #pragma unroll
     for (int q = 0; q < 6; ++q) b[q] = sp[q][lm];
@@ -274,55 +311,62 @@ __device__ inline void volume_sweep(const R (&own)[6], int i, int j, int k, cons
   }
 }
 
-// Surface correction of one face task (FP64): ((F*_c - F*_v) - (f_c - f_v)(own)) (+-1/w).
+// Surface correction of one face task (FP64):
+//   ((F*_c - F*_v) - (f_c - f_v)(own)) (+-1/w_end),
+// accumulated term by term to keep few values live.  so, sn: own and
+// neighbour conservative states at the face node; fvo, fvn: their normal
+// viscous fluxes.
 template <int d>
 __device__ inline void surface_correction(const double so[5], const double sn[5], bool wall,
                                           bool up, const double fvo[4], const double fvn[4],
                                           const DevPhys& ph, double inv_w, double corr[5]) {
-  const Prim Po = primitives(so, ph);
-  const double a[6] = {Po.rho, Po.u, Po.v, Po.w, Po.p, Po.e};
-  double fco[5];
+  const double iro = 1.0 / so[0];
+  const double a[6] = {so[0], so[1] * iro, so[2] * iro, so[3] * iro, 0.0, so[4] * iro};
+  const double po = ph.gm1 * (so[4] - 0.5 * so[0] * (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]));
+  double A[6] = {a[0], a[1], a[2], a[3], po, a[5]};
+  // minus the own physical flux (f_c - f_v)
   {
-    const double ud = a[1 + d];
-    const double mass = a[0] * ud;
-    fco[0] = mass;
-    fco[1] = mass * a[1];
-    fco[2] = mass * a[2];
-    fco[3] = mass * a[3];
-    fco[1 + d] += a[4];
-    fco[4] = (so[4] + a[4]) * ud;
+    const double ud = A[1 + d];
+    const double mass = A[0] * ud;
+    corr[0] = -mass;
+    corr[1] = -mass * A[1] + fvo[0];
+    corr[2] = -mass * A[2] + fvo[1];
+    corr[3] = -mass * A[3] + fvo[2];
+    corr[1 + d] -= po;
+    corr[4] = -(so[4] + po) * ud + fvo[3];
   }
-  double Fs[5];
   if (wall) {
     // isothermal no-slip wall: pressure-only convective flux; viscous flux
     // with zero wall velocity and the interior gradients (drops u . tau)
-    Fs[0] = Fs[1] = Fs[2] = Fs[3] = Fs[4] = 0.0;
-    Fs[1 + d] = a[4];
-    const double utau = a[1] * fvo[0] + a[2] * fvo[1] + a[3] * fvo[2];
-    Fs[1] -= fvo[0];
-    Fs[2] -= fvo[1];
-    Fs[3] -= fvo[2];
-    Fs[4] -= fvo[3] - utau;
+    corr[1 + d] += po;
+    corr[1] -= fvo[0];
+    corr[2] -= fvo[1];
+    corr[3] -= fvo[2];
+    corr[4] -= fvo[3] - (A[1] * fvo[0] + A[2] * fvo[1] + A[3] * fvo[2]);
   } else {
-    const Prim Pn = primitives(sn, ph);
-    const double b[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
-    kg_flux<d, double>(a, b, Fs);
+    const double irn = 1.0 / sn[0];
+    const double b1 = sn[1] * irn, b2 = sn[2] * irn, b3 = sn[3] * irn;
+    const double pn = ph.gm1 * (sn[4] - 0.5 * sn[0] * (b1 * b1 + b2 * b2 + b3 * b3));
+    const double B[6] = {sn[0], b1, b2, b3, pn, sn[4] * irn};
+    double F[5];
+    kg_flux<d, double>(A, B, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) corr[v] += F[v];
     if (!ph.central) {
-      const double cu = fabs(a[1 + d]) + sqrt(ph.gamma * Po.p / Po.rho);
-      const double cn = fabs(b[1 + d]) + sqrt(ph.gamma * Pn.p / Pn.rho);
+      const double cu = fabs(A[1 + d]) + sqrt(ph.gamma * po * iro);
+      const double cn = fabs(B[1 + d]) + sqrt(ph.gamma * pn * irn);
       const double lam = cu >= cn ? cu : cn;
       // -lambda/2 (U_R - U_L), L = the lower side of the face
-      const double sgn = up ? -0.5 : 0.5;
+      const double sl = (up ? -0.5 : 0.5) * lam;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Fs[v] += sgn * lam * (sn[v] - so[v]);
+      for (int v = 0; v < 5; ++v) corr[v] += sl * (sn[v] - so[v]);
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) Fs[1 + c] -= 0.5 * (fvo[c] + fvn[c]);
+    for (int c = 0; c < 4; ++c) corr[1 + c] -= 0.5 * (fvo[c] + fvn[c]);
   }
   const double sc = up ? inv_w : -inv_w;
-  corr[0] = (Fs[0] - fco[0]) * sc;
 #pragma unroll
-  for (int c = 0; c < 4; ++c) corr[1 + c] = (Fs[1 + c] - (fco[1 + c] - fvo[c])) * sc;
+  for (int v = 0; v < 5; ++v) corr[v] *= sc;
 }
 
 template <int N, typename R, bool RK, bool VISC>
@@ -336,7 +380,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB;
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
   constexpr bool MIXED = sizeof(R) == 4;
-  __shared__ R sD[NP * NP];
+  __shared__ R sD[NP * Gm::DS];
   __shared__ R sp[EPB][6][EB];      // rho, u, v, w, p - p_ref, e - e_ref
   __shared__ R sfv[EPB][4][EB];     // f_v,d of the current direction; [0] = T - T_ref in P1-P2
   __shared__ R sX[EPB][6][5][NF];   // lifting corrections (P1-P2), then surface corrections
@@ -347,25 +391,27 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   const long long nE = mesh.nE;
   const long long stride = nE * NN;
   const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
-  for (int t = tid; t < NP * NP; t += BS) sD[t] = static_cast<R>(basis.D[t]);
+  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * Gm::DS + t % NP] = static_cast<R>(basis.D[t]);
   const R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
 
-  const int le = tid / NN;
+  // with one element per workgroup the element index is wave-uniform
+  const int le = EPB == 1 ? 0 : tid / NN;
   const int node = tid - le * NN;
-  const long long e = e0 + le;
-  const bool active = le < EPB && e < nE;
+  const long long e = EPB == 1 ? e0 : e0 + le;
+  const bool active = (EPB == 1 ? tid < NN : le < EPB) && e < nE;
   const int i = node % NP, j = (node / NP) % NP, k = node / NF;
   const int l = Gm::lds(i, j, k);
+  int ex0 = 0, ey0 = 0, ez0 = 0;  // coordinates of element e0
+  elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
 
   // ---- P1: face lanes --------------------------------------------------
   const bool face_lane = tid < n_face_tasks<N>();
   if (face_lane && e0 + FaceTask<N>(tid).le < nE) {
     const FaceTask<N> ft(tid);
-    const long long te = e0 + ft.le;
-    long long nb;
-    int fx, fy, fz;
-    elem_coords(te, mesh, fx, fy, fz);
-    nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
+    const long long te = EPB == 1 ? e0 : e0 + ft.le;
+    int fx = ex0, fy = ey0, fz = ez0;
+    if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
+    const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
     if (VISC) {
       double so[5], sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
       load_state(U, stride, te * NN + ft.own_node(), so);
@@ -381,9 +427,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   // ---- P1: node lanes --------------------------------------------------
   R own[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
   double p_ref = 0.0, e_ref = 0.0;
-  int ex = 0, ey = 0, ez = 0;
+  int ex = ex0, ey = ey0, ez = ez0;
   if (active) {
-    elem_coords(e, mesh, ex, ey, ez);
+    if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
     double u0[5];
     load_state(U, stride, e * NN + node, u0);
     const Prim P = primitives(u0, ph);
@@ -456,13 +502,10 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   // ---- P4: surface corrections (face lanes, FP64) -----------------------
   if (face_lane && e0 + FaceTask<N>(tid).le < nE) {
     const FaceTask<N> ft(tid);
-    const long long te = e0 + ft.le;
-    long long nb;
-    {
-      int fx, fy, fz;
-      elem_coords(te, mesh, fx, fy, fz);
-      nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
-    }
+    const long long te = EPB == 1 ? e0 : e0 + ft.le;
+    int fx = ex0, fy = ey0, fz = ez0;
+    if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
+    const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
     // own and neighbour states at the face node: second reads, served by the
     // cache (this workgroup read the same lines in P1)
     const bool wall = nb < 0;

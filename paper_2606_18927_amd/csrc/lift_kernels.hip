@@ -18,7 +18,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_lift(const double* __restrict__ 
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB;
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
-  __shared__ double sD[NP * NP];
+  __shared__ double sD[NP * Gm::DS];
   __shared__ double sq[EPB][4][EB];
   __shared__ double ssq[EPB][6][4][NF];
 
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_lift(const double* __restrict__ 
   const long long nE = mesh.nE;
   const long long stride = nE * NN;
   const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
-  for (int t = tid; t < NP * NP; t += BS) sD[t] = basis.D[t];
+  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * Gm::DS + t % NP] = basis.D[t];
 
   const int le = tid / NN;
   const int node = tid - le * NN;
@@ -81,9 +81,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_lift(const double* __restrict__ 
       double ax = 0.0, ay = 0.0, az = 0.0;
 #pragma unroll
       for (int m = 0; m < NP; ++m) {
-        ax += sD[i * NP + m] * sq[le][c][Gm::lds(m, j, k)];
-        ay += sD[j * NP + m] * sq[le][c][Gm::lds(i, m, k)];
-        az += sD[k * NP + m] * sq[le][c][Gm::lds(i, j, m)];
+        ax += sD[i * Gm::DS + m] * sq[le][c][Gm::lds(m, j, k)];
+        ay += sD[j * Gm::DS + m] * sq[le][c][Gm::lds(i, m, k)];
+        az += sD[k * Gm::DS + m] * sq[le][c][Gm::lds(i, j, m)];
       }
       if (i == 0) ax += ssq[le][0][c][j + NP * k];
       if (i == N) ax += ssq[le][1][c][j + NP * k];
