@@ -52,6 +52,7 @@ typedef enum {
 
 #define DG_FP64 0
 #define DG_MIXED 1
+#define DG_MIXED_NOREF 2  /* DG_MIXED without the reference-state subtraction (measurement) */
 
 typedef struct dg_ctx dg_ctx;
 
@@ -71,8 +72,10 @@ typedef struct {
 typedef struct {
   double gamma, R, mu, Pr;
   int viscous;        /* 0: Euler fluxes only (no lifting), 1: Navier-Stokes      */
-  int precision;      /* DG_FP64, or DG_MIXED: FP32 lifting, volume and surface
-                         fluxes; FP64 state, primitive recovery, RK accumulation */
+  int precision;      /* DG_FP64, or DG_MIXED: FP32 lifting, volume fluxes and
+                         line sums; FP64 state, primitive recovery, surface
+                         fluxes and RK accumulation; p, e and T enter the FP32
+                         parts relative to a per-element reference value       */
   int central_only;   /* 1: drop the Lax-Friedrichs dissipation (test switch)     */
 } dg_physics;
 

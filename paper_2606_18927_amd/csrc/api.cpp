@@ -51,7 +51,7 @@ Layout layout(const dg_ctx* c) {
   const size_t NP = c->N + 1;
   const size_t dof = static_cast<size_t>(c->n_dof);
   const size_t state = 5 * dof * sizeof(double);
-  const size_t rsize = c->phys.precision == DG_MIXED ? sizeof(float) : sizeof(double);
+  const size_t rsize = c->phys.precision == DG_FP64 ? sizeof(double) : sizeof(float);
   const size_t fbytes = static_cast<size_t>(c->nE) * dg::face_flux_values_per_element(c->N) * rsize;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -102,6 +102,7 @@ dg::DevPhys dev_phys(const dg_ctx* c) {
   p.cv = c->phys.R / (c->phys.gamma - 1.0);
   p.viscous = c->phys.viscous;
   p.central = c->phys.central_only;
+  p.mixed_ref = c->phys.precision == DG_MIXED ? 1 : 0;
   return p;
 }
 
@@ -184,7 +185,9 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   if (nE > (1LL << 31) / 8 || nE * nn * 12 > (1LL << 40)) return DG_EINVAL;
   if (!(phys->gamma > 1.0) || !(phys->R > 0.0) || !(phys->mu >= 0.0) || !(phys->Pr > 0.0))
     return DG_EINVAL;
-  if (phys->precision != DG_FP64 && phys->precision != DG_MIXED) return DG_EINVAL;
+  if (phys->precision != DG_FP64 && phys->precision != DG_MIXED &&
+      phys->precision != DG_MIXED_NOREF)
+    return DG_EINVAL;
   if (mesh->bc[0] == DG_BC_ISOTHERMAL_WALL || mesh->bc[1] == DG_BC_ISOTHERMAL_WALL ||
       mesh->bc[2] == DG_BC_ISOTHERMAL_WALL) {
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;

@@ -28,6 +28,7 @@ struct DevMesh {
 struct DevPhys {
   double gamma, gm1, R, inv_R, mu, kappa, cv;
   int viscous, central;
+  int mixed_ref;      // mixed precision: subtract the element reference state
 };
 
 // LGL tables of one N, held in device memory inside the workspace.

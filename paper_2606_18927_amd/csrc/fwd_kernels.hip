@@ -130,7 +130,7 @@ template <typename R>
 __device__ inline void element_ref(const double* U, long long stride, long long e, int NN,
                                    const DevPhys& ph, double& p_ref, double& e_ref,
                                    double& T_ref) {
-  if (sizeof(R) == sizeof(double)) {
+  if (sizeof(R) == sizeof(double) || !ph.mixed_ref) {
     p_ref = e_ref = T_ref = 0.0;
     return;
   }
@@ -600,7 +600,7 @@ size_t face_flux_values_per_element(int N) { return static_cast<size_t>(6 * 4 * 
 hipError_t launch_face_flux(int N, int precision, const DevMesh& m, const DevPhys& p,
                             const DevBasis& b, const double* U, void* ffv, hipStream_t s) {
   if (m.nE <= 0 || !p.viscous) return hipSuccess;
-  const bool f32 = precision == DG_MIXED;
+  const bool f32 = precision != DG_FP64;
   switch (N) {
     case 3: return f32 ? face_flux_n<3, float>(m, p, b, U, ffv, s) : face_flux_n<3, double>(m, p, b, U, ffv, s);
     case 5: return f32 ? face_flux_n<5, float>(m, p, b, U, ffv, s) : face_flux_n<5, double>(m, p, b, U, ffv, s);
@@ -614,7 +614,7 @@ hipError_t launch_rhs(int N, int precision, const DevMesh& m, const DevPhys& p,
                       int* status, hipStream_t s) {
   if (m.nE <= 0) return hipSuccess;
   const Stage st{0.0, 0.0, 0.0, 0};
-  return precision == DG_MIXED
+  return precision != DG_FP64
              ? rhs_dispatch<float, false>(N, m, p, b, U, ffv, Ut, nullptr, st, status, s)
              : rhs_dispatch<double, false>(N, m, p, b, U, ffv, Ut, nullptr, st, status, s);
 }
@@ -623,7 +623,7 @@ hipError_t launch_rk_stage(int N, int precision, const DevMesh& m, const DevPhys
                            const DevBasis& b, const double* U, const void* ffv, double* G,
                            double* U_out, const Stage& st, int* status, hipStream_t s) {
   if (m.nE <= 0) return hipSuccess;
-  return precision == DG_MIXED
+  return precision != DG_FP64
              ? rhs_dispatch<float, true>(N, m, p, b, U, ffv, G, U_out, st, status, s)
              : rhs_dispatch<double, true>(N, m, p, b, U, ffv, G, U_out, st, status, s);
 }

@@ -24,7 +24,7 @@ DG_OK, DG_EINVAL, DG_ESTATE, DG_EHIP, DG_ENONPHYS, DG_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ESTATE", 3: "DG_EHIP", 4: "DG_ENONPHYS",
                 5: "DG_EUNSUPPORTED"}
 BC = {"periodic": 0, "wall": 1}
-PRECISION = {"fp64": 0, "mixed": 1}
+PRECISION = {"fp64": 0, "mixed": 1, "mixed_noref": 2}
 
 
 class DgsemError(RuntimeError):
