@@ -1,0 +1,493 @@
+// Vector-Jacobian product (adjoint) of the DGSEM right-hand side, FP64.
+//
+// Ubar = (dL/dU)^T lam is evaluated as a gather: every element computes the
+// cotangent of its own nodal state and pulls what its neighbours' equations
+// contribute through shared face nodes, so no atomics are needed and the
+// result is deterministic.  Two kernels (after k_lift has recomputed the
+// forward gradients of U):
+//
+//   k_vjp_a : lam (+ neighbour lam at face nodes), U, grad ->
+//             gbar = cotangent of the lifted gradients (12 per node) and the
+//             part of Ubar that does not pass through the lifting:
+//               * volume split form: for each line pair (i, m),
+//                 Pbar_i += -2 s_d J1(P_i, P_m)^T (D_im lam_i + D_mi lam_m),
+//                 J1 = d f#_KG(a, b) / d a (the flux is symmetric);
+//               * viscous volume term: Fvbar_d(m) = s_d sum_i D_im lam_i, then
+//                 the transpose of f_v,d(u, grad) -> (ubar, gbar);
+//               * each face node's numerical flux, which enters both sides'
+//                 equations, with the combined cotangent
+//                 phi = -(sc_o s_o lam_o + sc_n s_n lam_n)  (sc = +-1/w_end);
+//                 the own physical flux with -sc_o s_o lam_o;
+//               * the primitive map P(U) transposed.
+//   k_vjp_b : gbar (+ neighbour gbar at face nodes) -> qbar of q = (u, v, w, T)
+//             through the transposed BR1 lifting, then Ubar += (dq/dU)^T qbar.
+//
+// Non-smooth points: |u_d| and the max of the Lax-Friedrichs speed take the
+// derivative of the branch that is active (ties to the lower side L), as the
+// CPU oracle's reverse mode does.
+#include "dg_device.hpp"
+
+namespace dg {
+namespace {
+
+// abar += (d f#_d(a, b) / d a)^T mu, a and b primitive (rho, u, v, w, p, e).
+template <int d>
+__device__ inline void kg_vjp(const double a[6], const double b[6], const double mu[5],
+                              double abar[6]) {
+  const double rho = 0.5 * (a[0] + b[0]);
+  const double u0 = 0.5 * (a[1] + b[1]), u1 = 0.5 * (a[2] + b[2]), u2 = 0.5 * (a[3] + b[3]);
+  const double p = 0.5 * (a[4] + b[4]);
+  const double e = 0.5 * (a[5] + b[5]);
+  const double ud = d == 0 ? u0 : (d == 1 ? u1 : u2);
+  const double mass = rho * ud;
+  const double S = mu[0] + u0 * mu[1] + u1 * mu[2] + u2 * mu[3] + e * mu[4];
+  abar[0] += 0.5 * ud * S;
+  abar[1] += 0.5 * mass * mu[1];
+  abar[2] += 0.5 * mass * mu[2];
+  abar[3] += 0.5 * mass * mu[3];
+  abar[1 + d] += 0.5 * (rho * S + p * mu[4]);
+  abar[4] += 0.5 * (mu[1 + d] + ud * mu[4]);
+  abar[5] += 0.5 * mass * mu[4];
+}
+
+// abar += (d f_d(a) / d a)^T mu for the Euler flux
+// f = (rho u_d, rho u u_d + p e_d, (rho e + p) u_d).
+template <int d>
+__device__ inline void euler_vjp(const double a[6], const double mu[5], double abar[6]) {
+  const double rho = a[0], ud = a[1 + d], p = a[4], e = a[5];
+  const double Sk = a[1] * mu[1] + a[2] * mu[2] + a[3] * mu[3];
+  abar[0] += ud * (mu[0] + Sk + e * mu[4]);
+  abar[1] += rho * ud * mu[1];
+  abar[2] += rho * ud * mu[2];
+  abar[3] += rho * ud * mu[3];
+  abar[1 + d] += rho * (mu[0] + Sk) + (rho * e + p) * mu[4];
+  abar[4] += mu[1 + d] + ud * mu[4];
+  abar[5] += rho * ud * mu[4];
+}
+
+// Ubar += (dP/dU)^T Pbar + (dT/dU)^T Tbar, P = (rho, u, v, w, p, e), T = p/(rho R).
+__device__ inline void prim_vjp(const double s[5], const double Pb[6], double Tb,
+                                const DevPhys& ph, double Ub[5]) {
+  const double ir = 1.0 / s[0];
+  const double u = s[1] * ir, v = s[2] * ir, w = s[3] * ir;
+  const double q2 = u * u + v * v + w * w;
+  const double p = ph.gm1 * (s[4] - 0.5 * s[0] * q2);
+  const double e = s[4] * ir;
+  const double T = p * ph.inv_R * ir;
+  const double pb = Pb[4] + Tb * ir * ph.inv_R;
+  const double rb = Pb[0] - Tb * T * ir;
+  Ub[0] += rb - ir * (u * Pb[1] + v * Pb[2] + w * Pb[3]) + 0.5 * ph.gm1 * q2 * pb - e * ir * Pb[5];
+  Ub[1] += ir * Pb[1] - ph.gm1 * u * pb;
+  Ub[2] += ir * Pb[2] - ph.gm1 * v * pb;
+  Ub[3] += ir * Pb[3] - ph.gm1 * w * pb;
+  Ub[4] += ph.gm1 * pb + ir * Pb[5];
+}
+
+// abar += lb d(|u_d| + c)/dP, c = sqrt(gamma p / rho).
+template <int d>
+__device__ inline void speed_vjp(const double a[6], double lb, const DevPhys& ph, double abar[6]) {
+  const double c = sqrt(ph.gamma * a[4] / a[0]);
+  const double ud = a[1 + d];
+  abar[1 + d] += lb * (ud > 0.0 ? 1.0 : (ud < 0.0 ? -1.0 : 0.0));
+  abar[4] += lb * 0.5 * c / a[4];
+  abar[0] -= lb * 0.5 * c / a[0];
+}
+
+__device__ inline void to_prim(const double s[5], const DevPhys& ph, double a[6]) {
+  const Prim P = primitives(s, ph);
+  a[0] = P.rho;
+  a[1] = P.u;
+  a[2] = P.v;
+  a[3] = P.w;
+  a[4] = P.p;
+  a[5] = P.e;
+}
+
+// Cotangents of one face node of the own element (o) in k_vjp_a: the state
+// cotangent Ud (the primitive map already applied), the cotangent Fvb of the
+// own normal viscous flux f_v,d, and om, the cotangent of the u . tau_d term
+// that a wall removes from the viscous flux.
+template <int d>
+__device__ inline void face_vjp(const double so[5], const double lo[5], const double sn[5],
+                                const double ln[5], bool wall, bool up, double s_o, double s_n,
+                                const DevPhys& ph, double inv_w, double Ud[5], double Fvb[4],
+                                double& om) {
+  double Po[6];
+  to_prim(so, ph, Po);
+  const double sc_o = up ? inv_w : -inv_w;
+  double psi[5], phi[5], Pb[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int v = 0; v < 5; ++v) psi[v] = -sc_o * s_o * lo[v];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Ud[v] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Fvb[c] = 0.0;
+  om = 0.0;
+  if (wall) {
+    // F*_c = (0, p_o e_d, 0); F*_v = f_v,o - (0, 0, 0, 0, u . tau_d)
+    Pb[4] += psi[1 + d];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Fvb[c] -= psi[1 + c];
+    om += psi[4];
+  } else {
+    double Pn[6];
+    to_prim(sn, ph, Pn);
+    const double sc_n = -sc_o;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) phi[v] = psi[v] - sc_n * s_n * ln[v];
+    kg_vjp<d>(Po, Pn, phi, Pb);
+    if (!ph.central) {
+      const double co = fabs(Po[1 + d]) + sqrt(ph.gamma * Po[4] / Po[0]);
+      const double cn = fabs(Pn[1 + d]) + sqrt(ph.gamma * Pn[4] / Pn[0]);
+      // the own element is the lower side L of the face when the face is its upper one
+      const bool own_L = up;
+      const double lam = own_L ? (co >= cn ? co : cn) : (cn >= co ? cn : co);
+      const bool own_active = own_L ? (co >= cn) : (co > cn);
+      // F*_c contains -lam/2 (U_R - U_L)
+      const double dU = own_L ? 0.5 * lam : -0.5 * lam;
+      double lb = 0.0;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        Ud[v] += dU * phi[v];
+        const double jump = own_L ? sn[v] - so[v] : so[v] - sn[v];
+        lb -= 0.5 * phi[v] * jump;
+      }
+      if (own_active) speed_vjp<d>(Po, lb, ph, Pb);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Fvb[c] -= 0.5 * phi[1 + c];
+  }
+  // the own physical flux -(f_c - f_v)(o) of the own equation
+  double mpsi[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) mpsi[v] = -psi[v];
+  euler_vjp<d>(Po, mpsi, Pb);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Fvb[c] += psi[1 + c];
+  prim_vjp(so, Pb, 0.0, ph, Ud);
+}
+
+// Scale s_d of the neighbour across face (d, up) of element (ex, ey, ez).
+__device__ inline double nb_scale(const DevMesh& m, int ex, int ey, int ez, int d, bool up) {
+  const int c = d == 0 ? ex : (d == 1 ? ey : ez);
+  int v = c + (up ? 1 : -1);
+  if (v < 0) v = m.n[d] - 1;
+  if (v >= m.n[d]) v = 0;
+  return m.s[d][v];
+}
+
+// --------------------------------------------------------------------------
+// k_vjp_a
+// --------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_a(const double* __restrict__ U,
+                                                       const double* __restrict__ grad,
+                                                       const double* __restrict__ lam,
+                                                       double* __restrict__ gbar,
+                                                       double* __restrict__ ubar, DevMesh mesh,
+                                                       DevPhys ph, DevBasis basis) {
+  using Gm = Geo<N>;
+  constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB, DS = Gm::DS;
+  constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
+  __shared__ double sD[NP * DS];
+  __shared__ double sP[EPB][6][EB];
+  __shared__ double sL[EPB][5][EB];
+  __shared__ double sFU[EPB][6][5][NF];
+  __shared__ double sFV[EPB][6][5][NF];
+
+  const int tid = threadIdx.x;
+  const long long nE = mesh.nE;
+  const long long stride = nE * NN;
+  const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
+  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * DS + t % NP] = basis.D[t];
+  int ex0 = 0, ey0 = 0, ez0 = 0;
+  elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
+
+  const int le = EPB == 1 ? 0 : tid / NN;
+  const int node = tid - le * NN;
+  const long long e = EPB == 1 ? e0 : e0 + le;
+  const bool active = (EPB == 1 ? tid < NN : le < EPB) && e < nE;
+  const int i = node % NP, j = (node / NP) % NP, k = node / NF;
+  const int l = Gm::lds(i, j, k);
+
+  // P1: node lanes stage primitives and lam; face lanes form the face cotangents
+  double own[6] = {0, 0, 0, 0, 0, 0}, lo[5] = {0, 0, 0, 0, 0};
+  int ex = ex0, ey = ey0, ez = ez0;
+  if (active) {
+    if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
+    double s[5];
+    load_state(U, stride, e * NN + node, s);
+    to_prim(s, ph, own);
+    load_state(lam, stride, e * NN + node, lo);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) sP[le][q][l] = own[q];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sL[le][v][l] = lo[v];
+  }
+  if (tid < n_face_tasks<N>()) {
+    const FaceTask<N> ft(tid);
+    const long long te = EPB == 1 ? e0 : e0 + ft.le;
+    if (te < nE) {
+      int fx = ex0, fy = ey0, fz = ez0;
+      if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
+      const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
+      const bool wall = nb < 0;
+      const long long oidx = te * NN + ft.own_node();
+      double so[5], fl[5], sn[5] = {1, 0, 0, 0, 1}, ln[5] = {0, 0, 0, 0, 0};
+      load_state(U, stride, oidx, so);
+      load_state(lam, stride, oidx, fl);
+      double s_n = 0.0;
+      if (!wall) {
+        const long long nidx = nb * NN + ft.nb_node();
+        load_state(U, stride, nidx, sn);
+        load_state(lam, stride, nidx, ln);
+        s_n = nb_scale(mesh, fx, fy, fz, ft.d, ft.up);
+      }
+      const double s_o = mesh.s[ft.d][ft.d == 0 ? fx : (ft.d == 1 ? fy : fz)];
+      double Ud[5], Fvb[4], om;
+      if (ft.d == 0)
+        face_vjp<0>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
+      else if (ft.d == 1)
+        face_vjp<1>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
+      else
+        face_vjp<2>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sFU[ft.le][ft.f][v][ft.ab] = Ud[v];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sFV[ft.le][ft.f][c][ft.ab] = Fvb[c];
+      sFV[ft.le][ft.f][4][ft.ab] = om;
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+
+  // P2: node lanes
+  const bool visc = ph.viscous != 0;
+  const double mu = ph.mu, kappa = ph.kappa;
+  double g[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) g[c] = visc ? grad[c * stride + e * NN + node] : 0.0;
+  // stress tau_ab (a, b in 0..2), symmetric
+  const double dv = (2.0 / 3.0) * (g[0] + g[4] + g[8]);
+  double tau[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) tau[3 * a + b] = mu * (g[3 * a + b] + g[3 * b + a] - (a == b ? dv : 0.0));
+
+  double Pb[6] = {0, 0, 0, 0, 0, 0};
+  double tb[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  double gT[3] = {0, 0, 0};
+  double Ub[5] = {0, 0, 0, 0, 0};
+
+#define DG_ADJ_DIRECTION(D)                                                                    \
+  {                                                                                            \
+    const int idx = D == 0 ? i : (D == 1 ? j : k);                                             \
+    const int ab = D == 0 ? j + NP * k : (D == 1 ? i + NP * k : i + NP * j);                   \
+    const double sd = mesh.s[D][D == 0 ? ex : (D == 1 ? ey : ez)];                              \
+    double Fv[4] = {0, 0, 0, 0};                                                               \
+    _Pragma("unroll") for (int m = 0; m < NP; ++m) {                                           \
+      const int lm = D == 0 ? Gm::lds(m, j, k) : (D == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m)); \
+      const double Dim = sD[idx * DS + m], Dmi = sD[m * DS + idx];                              \
+      double b[6], lmv[5], mu5[5];                                                             \
+      _Pragma("unroll") for (int q = 0; q < 6; ++q) b[q] = sP[le][q][lm];                      \
+      _Pragma("unroll") for (int v = 0; v < 5; ++v) lmv[v] = sL[le][v][lm];                    \
+      _Pragma("unroll") for (int v = 0; v < 5; ++v) mu5[v] = -2.0 * sd * (Dim * lo[v] + Dmi * lmv[v]); \
+      kg_vjp<D>(own, b, mu5, Pb);                                                              \
+      _Pragma("unroll") for (int c = 0; c < 4; ++c) Fv[c] += sd * Dmi * lmv[1 + c];             \
+    }                                                                                          \
+    double omd = 0.0;                                                                          \
+    if (idx == 0) {                                                                            \
+      _Pragma("unroll") for (int c = 0; c < 4; ++c) Fv[c] += sFV[le][2 * D][c][ab];            \
+      omd += sFV[le][2 * D][4][ab];                                                            \
+      _Pragma("unroll") for (int v = 0; v < 5; ++v) Ub[v] += sFU[le][2 * D][v][ab];            \
+    }                                                                                          \
+    if (idx == N) {                                                                            \
+      _Pragma("unroll") for (int c = 0; c < 4; ++c) Fv[c] += sFV[le][2 * D + 1][c][ab];        \
+      omd += sFV[le][2 * D + 1][4][ab];                                                        \
+      _Pragma("unroll") for (int v = 0; v < 5; ++v) Ub[v] += sFU[le][2 * D + 1][v][ab];        \
+    }                                                                                          \
+    if (visc) {                                                                                \
+      const double eb = Fv[3] + omd;                                                           \
+      _Pragma("unroll") for (int a = 0; a < 3; ++a) {                                          \
+        tb[3 * a + D] += Fv[a] + eb * own[1 + a];                                              \
+        Pb[1 + a] += eb * tau[3 * a + D];                                                      \
+      }                                                                                        \
+      gT[D] += kappa * Fv[3];                                                                  \
+    }                                                                                          \
+  }
+  DG_ADJ_DIRECTION(0)
+  DG_ADJ_DIRECTION(1)
+  DG_ADJ_DIRECTION(2)
+#undef DG_ADJ_DIRECTION
+
+  const long long idx = e * NN + node;
+  if (visc) {
+    const double tr = tb[0] + tb[4] + tb[8];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+#pragma unroll
+      for (int y = 0; y < 3; ++y)
+        gbar[(3 * x + y) * stride + idx] =
+            mu * (tb[3 * x + y] + tb[3 * y + x]) - (x == y ? (2.0 / 3.0) * mu * tr : 0.0);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gbar[(9 + d) * stride + idx] = gT[d];
+  }
+  double s[5];
+  load_state(U, stride, idx, s);
+  prim_vjp(s, Pb, 0.0, ph, Ub);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) ubar[v * stride + idx] = Ub[v];
+}
+
+// --------------------------------------------------------------------------
+// k_vjp_b: transposed lifting
+// --------------------------------------------------------------------------
+template <int N, bool ACC>
+__global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_b(const double* __restrict__ U,
+                                                       const double* __restrict__ gbar,
+                                                       const double* __restrict__ ubar,
+                                                       double* __restrict__ out, double scale,
+                                                       DevMesh mesh, DevPhys ph,
+                                                       DevBasis basis) {
+  using Gm = Geo<N>;
+  constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB, DS = Gm::DS;
+  constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
+  __shared__ double sD[NP * DS];
+  __shared__ double sG[EPB][12][EB];
+  __shared__ double sQ[EPB][6][4][NF];
+
+  const int tid = threadIdx.x;
+  const long long nE = mesh.nE;
+  const long long stride = nE * NN;
+  const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
+  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * DS + t % NP] = basis.D[t];
+  int ex0 = 0, ey0 = 0, ez0 = 0;
+  elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
+
+  const int le = EPB == 1 ? 0 : tid / NN;
+  const int node = tid - le * NN;
+  const long long e = EPB == 1 ? e0 : e0 + le;
+  const bool active = (EPB == 1 ? tid < NN : le < EPB) && e < nE;
+  const int i = node % NP, j = (node / NP) % NP, k = node / NF;
+  const int l = Gm::lds(i, j, k);
+  const bool visc = ph.viscous != 0;
+
+  if (active && visc) {
+#pragma unroll
+    for (int c = 0; c < 12; ++c) sG[le][c][l] = gbar[c * stride + e * NN + node];
+  }
+  __syncthreads();
+  if (visc && tid < n_face_tasks<N>()) {
+    const FaceTask<N> ft(tid);
+    const long long te = EPB == 1 ? e0 : e0 + ft.le;
+    if (te < nE) {
+      int fx = ex0, fy = ey0, fz = ez0;
+      if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
+      const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
+      const double s_o = mesh.s[ft.d][ft.d == 0 ? fx : (ft.d == 1 ? fy : fz)];
+      const double sgn = (ft.up ? -1.0 : 1.0) * basis.inv_w_end;
+      const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
+      if (nb < 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sQ[ft.le][ft.f][c][ft.ab] = sgn * s_o * sG[ft.le][3 * c + ft.d][lo];
+      } else {
+        const double s_n = nb_scale(mesh, fx, fy, fz, ft.d, ft.up);
+        const long long nidx = nb * NN + ft.nb_node();
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          sQ[ft.le][ft.f][c][ft.ab] =
+              0.5 * sgn * (s_o * sG[ft.le][3 * c + ft.d][lo] + s_n * gbar[(3 * c + ft.d) * stride + nidx]);
+      }
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+
+  int ex = ex0, ey = ey0, ez = ez0;
+  if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
+  const long long idx = e * NN + node;
+  double Ub[5];
+  load_state(ubar, stride, idx, Ub);
+  if (visc) {
+    const double sx = mesh.s[0][ex], sy = mesh.s[1][ey], sz = mesh.s[2][ez];
+    double qb[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        ax += sD[m * DS + i] * sG[le][3 * c + 0][Gm::lds(m, j, k)];
+        ay += sD[m * DS + j] * sG[le][3 * c + 1][Gm::lds(i, m, k)];
+        az += sD[m * DS + k] * sG[le][3 * c + 2][Gm::lds(i, j, m)];
+      }
+      qb[c] = sx * ax + sy * ay + sz * az;
+      if (i == 0) qb[c] += sQ[le][0][c][j + NP * k];
+      if (i == N) qb[c] += sQ[le][1][c][j + NP * k];
+      if (j == 0) qb[c] += sQ[le][2][c][i + NP * k];
+      if (j == N) qb[c] += sQ[le][3][c][i + NP * k];
+      if (k == 0) qb[c] += sQ[le][4][c][i + NP * j];
+      if (k == N) qb[c] += sQ[le][5][c][i + NP * j];
+    }
+    double s[5];
+    load_state(U, stride, idx, s);
+    const double Pb[6] = {0.0, qb[0], qb[1], qb[2], 0.0, 0.0};
+    prim_vjp(s, Pb, qb[3], ph, Ub);
+  }
+  if (ACC) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v * stride + idx] += scale * Ub[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) out[v * stride + idx] = Ub[v];
+  }
+}
+
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b,
+                        long long n) {
+  for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
+       t += static_cast<long long>(gridDim.x) * blockDim.x)
+    y[t] = a * y[t] + b * x[t];
+}
+
+template <int N>
+hipError_t vjp_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
+                 const double* grad, const double* lam, double* gbar, double* ubar, double* out,
+                 bool acc, double scale, hipStream_t s) {
+  hipLaunchKernelGGL((k_vjp_a<N>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U, grad, lam,
+                     gbar, ubar, m, p, b);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (acc)
+    hipLaunchKernelGGL((k_vjp_b<N, true>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U,
+                       gbar, ubar, out, scale, m, p, b);
+  else
+    hipLaunchKernelGGL((k_vjp_b<N, false>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U,
+                       gbar, ubar, out, scale, m, p, b);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                          const double* U, const double* grad, const double* lam, double* gbar,
+                          double* ubar, double* out, bool accumulate, double scale,
+                          hipStream_t s) {
+  if (m.nE <= 0) return hipSuccess;
+  switch (N) {
+    case 3: return vjp_n<3>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, s);
+    case 5: return vjp_n<5>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, s);
+    case 7: return vjp_n<7>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_axpby, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, y, x, a, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace dg

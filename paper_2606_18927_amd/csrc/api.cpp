@@ -42,7 +42,7 @@ dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
 
 struct Layout {
   size_t D, w, s[3], status, partial, U0, U1, G, ffv;
-  size_t stages, lamG, lamU, ubar, gbar, tmp;
+  size_t stages, lamG, lamU, ubar, gbar, agrad, tmp;
   size_t fwd_end, adj_end;
 };
 
@@ -74,6 +74,7 @@ Layout layout(const dg_ctx* c) {
   L.lamU = take(state);
   L.ubar = take(state);
   L.gbar = take(12 * dof * sizeof(double));
+  L.agrad = take(12 * dof * sizeof(double));
   L.tmp = take(state);
   L.adj_end = off;
   return L;
@@ -257,11 +258,11 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
     c->lamG = reinterpret_cast<double*>(ws + L.lamG);
     c->lamU = reinterpret_cast<double*>(ws + L.lamU);
     c->ubar = reinterpret_cast<double*>(ws + L.ubar);
-    c->gbar = static_cast<void*>(ws + L.gbar);
+    c->gbar = reinterpret_cast<double*>(ws + L.gbar);
+    c->agrad = reinterpret_cast<double*>(ws + L.agrad);
     c->tmp = reinterpret_cast<double*>(ws + L.tmp);
   } else {
-    c->stages = c->lamG = c->lamU = c->ubar = c->tmp = nullptr;
-    c->gbar = nullptr;
+    c->stages = c->lamG = c->lamU = c->ubar = c->tmp = c->gbar = c->agrad = nullptr;
   }
   c->adjoint_bound = with_adjoint != 0;
   const size_t NP = c->N + 1;
@@ -354,12 +355,72 @@ dg_status dg_rk_step(dg_ctx* c, double /*t*/, double dt, int nsteps) {
   return DG_OK;
 }
 
-dg_status dg_eval_rhs_vjp(dg_ctx* c, const double*, const double*, double*, double) {
-  return fail(c, DG_EUNSUPPORTED, "eval_rhs_vjp not built yet");
+dg_status dg_eval_rhs_vjp(dg_ctx* c, const double* U, const double* lam, double* Ubar, double /*t*/) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
+  if (!U || !lam || !Ubar || Ubar == U || Ubar == lam) return fail(c, DG_EINVAL, "bad pointers");
+  const dg::DevMesh m = dev_mesh(c);
+  const dg::DevPhys p = dev_phys(c);
+  const dg::DevBasis b = dev_basis(c);
+  if (c->phys.viscous &&
+      (st = hip_check(c, dg::launch_lift(c->N, m, p, b, U, c->agrad, c->stream), "lift kernel")) != DG_OK)
+    return st;
+  return hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, U, c->agrad, lam, c->gbar, c->ubar, Ubar, false,
+                                         1.0, c->stream),
+                   "vjp kernels");
 }
 
-dg_status dg_rk_step_vjp(dg_ctx* c, const double*, double, double, const double*, double*) {
-  return fail(c, DG_EUNSUPPORTED, "rk_step_vjp not built yet");
+dg_status dg_rk_step_vjp(dg_ctx* c, const double* U_n, double /*t*/, double dt, const double* lam_np1,
+                         double* lam_n) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
+  if (!U_n || !lam_np1 || !lam_n || !std::isfinite(dt)) return fail(c, DG_EINVAL, "bad arguments");
+  const dg::DevMesh m = dev_mesh(c);
+  const dg::DevPhys p = dev_phys(c);
+  const dg::DevBasis b = dev_basis(c);
+  const long long n5 = 5 * c->n_dof;
+  const size_t bytes = n5 * sizeof(double);
+  auto stage_state = [&](int s) { return c->stages + static_cast<size_t>(s) * n5; };
+  // forward recompute of the five stage inputs with the context's own forward
+  if ((st = hip_check(c, hipMemcpyAsync(stage_state(0), U_n, bytes, hipMemcpyDeviceToDevice, c->stream),
+                      "stage copy")) != DG_OK)
+    return st;
+  for (int s = 0; s < 5; ++s) {
+    if (c->phys.viscous &&
+        (st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, stage_state(s), c->ffv,
+                                                c->stream),
+                        "face flux kernel")) != DG_OK)
+      return st;
+    const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
+    double* out = s < 4 ? stage_state(s + 1) : c->tmp;
+    if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, stage_state(s), c->ffv,
+                                               c->G, out, stage, c->dstatus, c->stream),
+                        "rk stage kernel")) != DG_OK)
+      return st;
+  }
+  // reverse sweep: cot_s = A_{s+1} cot_{s+1} + B_s lamU;  lamU += dt (dL/dU(U_s))^T cot_s
+  if ((st = hip_check(c, hipMemcpyAsync(c->lamU, lam_np1, bytes, hipMemcpyDeviceToDevice, c->stream),
+                      "lam copy")) != DG_OK)
+    return st;
+  if ((st = hip_check(c, hipMemsetAsync(c->lamG, 0, bytes, c->stream), "clear lamG")) != DG_OK) return st;
+  for (int s = 4; s >= 0; --s) {
+    const double a_next = s < 4 ? kRkA[s + 1] : 0.0;
+    if ((st = hip_check(c, dg::launch_axpby(c->lamG, c->lamU, a_next, kRkB[s], n5, c->stream),
+                        "axpby kernel")) != DG_OK)
+      return st;
+    if (c->phys.viscous &&
+        (st = hip_check(c, dg::launch_lift(c->N, m, p, b, stage_state(s), c->agrad, c->stream),
+                        "lift kernel")) != DG_OK)
+      return st;
+    if ((st = hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, stage_state(s), c->agrad, c->lamG, c->gbar,
+                                              c->ubar, c->lamU, true, dt, c->stream),
+                        "vjp kernels")) != DG_OK)
+      return st;
+  }
+  return hip_check(c, hipMemcpyAsync(lam_n, c->lamU, bytes, hipMemcpyDeviceToDevice, c->stream),
+                   "lam copy");
 }
 
 dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double* J) {

@@ -58,6 +58,16 @@ hipError_t launch_rk_stage(int N, int precision, const DevMesh& m, const DevPhys
 hipError_t launch_lift(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
                        const double* U, double* grad, hipStream_t s);
 
+// Adjoint (adj_kernels.hip): Ubar = (dL/dU)^T lam at U, given the forward
+// gradients grad of U; gbar and ubar are scratch (12 and 5 values per DOF).
+// accumulate: out += scale * Ubar, else out = Ubar.
+hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                          const double* U, const double* grad, const double* lam, double* gbar,
+                          double* ubar, double* out, bool accumulate, double scale,
+                          hipStream_t s);
+// y = a y + b x over n doubles.
+hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
+
 // Reductions and elementwise kernels (aux_kernels.hip).
 hipError_t launch_kinetic_energy(int N, const DevMesh& m, const double* w, const double* U,
                                  double* partial, int n_partial, double inv_vol, double* J,
@@ -105,7 +115,8 @@ struct dg_ctx {
   double* lamG = nullptr;
   double* lamU = nullptr;
   double* ubar = nullptr;     // per-node partial cotangent of the state
-  void* gbar = nullptr;       // cotangent of the lifted gradients
+  double* gbar = nullptr;     // cotangent of the lifted gradients
+  double* agrad = nullptr;    // forward lifted gradients of the stage being reversed
   double* tmp = nullptr;      // one state of scratch
 
   // measurement: one event after each timed launch (kernel class 0 = lift, 1 = rhs)

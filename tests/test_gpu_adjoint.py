@@ -1,0 +1,169 @@
+"""Adjoint (vector-Jacobian product) of the HIP operator against the oracle (GPU).
+
+* dg_eval_rhs_vjp vs the oracle's reverse-mode VJP, per variable rel L2;
+* <Ubar_gpu, v> vs <lam, (dL/dU) v> with the oracle's complex-step JVP;
+* dg_rk_step_vjp vs the oracle's reverse mode through one RK step;
+* the kinetic-energy gradient of a short rollout (checkpointed) vs the oracle;
+* the N = 5, 16^3-element stretched channel, 50 steps: directional derivatives
+  of the gradient vs central finite differences of the FP64 GPU forward on 20
+  seeded directions.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.adjoint import rhs_jvp_cs, rhs_vjp, rollout_grad
+from oracle.dgsem import rk_step
+from paper_2606_18927_amd import dgsem, workloads
+from paper_2606_18927_amd.autograd import kinetic_energy_gradient, rollout
+
+from _cases import random_faces, random_state
+from _gpu import custom, need_gpu, oracle_gas, oracle_mesh, rel_l2, say, state, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def _random_case(N, n, bc, seed, mu=0.01):
+    from oracle.mesh import Mesh
+    from oracle.physics import Gas
+    rng = np.random.default_rng(seed)
+    faces = [random_faces(n[d], -1.0, 1.0, rng) if bc[d] == "wall" else random_faces(n[d], 0.0, 2.0 + d, rng)
+             for d in range(3)]
+    mesh = Mesh(N, tuple(faces), bc=bc, T_wall=1.1)
+    g = Gas(gamma=1.4, R=1.0 / (1.4 * 0.01), mu=mu, Pr=0.72)
+    U = random_state(mesh, g.gamma, g.R, rng, vel_amp=1.0, p_mean=1.0 / (1.4 * 0.01), p_amp=0.05)
+    lam = torch.tensor(rng.standard_normal(U.shape))
+    return mesh, g, U.numpy(), lam.numpy()
+
+
+def _solver(mesh, g, **kw):
+    spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall)
+    return dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, with_adjoint=True, **kw)
+
+
+@pytest.mark.parametrize("N,n,bc", [
+    (3, (3, 2, 3), ("periodic",) * 3),
+    (3, (2, 3, 2), ("periodic", "wall", "periodic")),
+    (5, (2, 3, 2), ("periodic", "wall", "periodic")),
+    (7, (2, 2, 3), ("periodic",) * 3),
+])
+def test_eval_rhs_vjp_against_oracle(N, n, bc):
+    need_gpu()
+    say("vjp case", N, n, bc)
+    mesh, g, U, lam = _random_case(N, n, bc, seed=17 + N)
+    S = _solver(mesh, g)
+    got = S.eval_rhs_vjp(to_dev(U), to_dev(lam)).cpu().numpy()
+    S.sync()
+    ref = rhs_vjp(torch.as_tensor(U), torch.as_tensor(lam), mesh, g).numpy()
+    e = rel_l2(got, ref)
+    say("  rel L2", e)
+    assert np.all(e < TOL)
+
+
+@pytest.mark.parametrize("viscous,central", [(False, False), (False, True), (True, True)])
+def test_eval_rhs_vjp_switches(viscous, central):
+    need_gpu()
+    mesh, g, U, lam = _random_case(3, (2, 3, 2), ("periodic", "wall", "periodic"), seed=5)
+    S = _solver(mesh, g, viscous=viscous, central_only=central)
+    got = S.eval_rhs_vjp(to_dev(U), to_dev(lam)).cpu().numpy()
+    ref = rhs_vjp(torch.as_tensor(U), torch.as_tensor(lam), mesh, g, viscous=viscous,
+                  central_only=central).numpy()
+    e = rel_l2(got, ref)
+    say("switches", viscous, central, e)
+    assert np.all(e < TOL)
+
+
+def test_vjp_dot_product_with_complex_step_jvp():
+    need_gpu()
+    mesh, g, U, lam = _random_case(5, (2, 2, 2), ("periodic", "periodic", "wall"), seed=23)
+    rng = np.random.default_rng(24)
+    S = _solver(mesh, g)
+    Ubar = S.eval_rhs_vjp(to_dev(U), to_dev(lam)).cpu().numpy()
+    for _ in range(3):
+        v = rng.standard_normal(U.shape)
+        jv = rhs_jvp_cs(torch.as_tensor(U), torch.as_tensor(v), mesh, g).numpy()
+        lhs, rhs_ = float((lam * jv).sum()), float((Ubar.reshape(U.shape) * v).sum())
+        say("dot", lhs, rhs_)
+        assert abs(lhs - rhs_) < 1e-11 * (abs(lhs) + 1.0)
+
+
+@pytest.mark.parametrize("name", ["tgv_n3", "channel_n5"])
+def test_rk_step_vjp_against_oracle(name):
+    need_gpu()
+    if name == "tgv_n3":
+        wl = custom("tgv", 3, (3, 3, 2), noise=0.01, seed=3)
+    else:
+        wl = custom("channel", 5, (2, 3, 2), seed=workloads.CHANNEL_SEED)
+    U, dt = state(wl)
+    mesh, g = oracle_mesh(wl), oracle_gas(wl)
+    rng = np.random.default_rng(31)
+    lam = rng.standard_normal(U.shape)
+    Ut = torch.as_tensor(U).requires_grad_(True)
+    (ref,) = torch.autograd.grad(rk_step(Ut, mesh, g, dt, 1), Ut, grad_outputs=torch.as_tensor(lam))
+    S = dgsem.solver_for(wl, with_adjoint=True)
+    got = S.rk_step_vjp(to_dev(U), dt, to_dev(lam)).cpu().numpy()
+    S.sync()
+    e = rel_l2(got, ref.numpy())
+    d = rel_l2(got - lam.reshape(5, -1).reshape(got.shape), ref.numpy() - lam)
+    say(name, "rk vjp rel L2", e, "minus identity", d)
+    assert np.all(e < TOL)
+    assert np.all(d < 1e-9)
+
+
+def test_rollout_kinetic_energy_gradient_against_oracle():
+    need_gpu()
+    wl = custom("channel", 3, (2, 3, 2), seed=workloads.CHANNEL_SEED)
+    U, dt = state(wl)
+    mesh, g = oracle_mesh(wl), oracle_gas(wl)
+    nsteps = 6
+    Jref, gref = rollout_grad(torch.as_tensor(U), mesh, g, dt, nsteps)
+    S = dgsem.solver_for(wl, with_adjoint=True)
+    J, grad = kinetic_energy_gradient(S, to_dev(U), dt, nsteps, checkpoint_every=4)
+    J = J.item()
+    grad = grad.cpu().numpy()
+    say("J", J, Jref.item())
+    assert abs(J - Jref.item()) < 1e-13 * abs(Jref.item())
+    e = rel_l2(grad, gref.numpy())
+    say("rollout gradient rel L2", e)
+    # (d J / d E) vanishes identically only at t = 0; after the rollout all five are nonzero
+    assert np.all(e < 1e-10)
+    # the autograd.Function gives the same gradient through torch
+    Ud = to_dev(U).requires_grad_(True)
+    UT = rollout(Ud, S, dt, nsteps, 4)
+    lamT = S.kinetic_energy_grad(UT.detach())
+    (g2,) = torch.autograd.grad(UT, Ud, grad_outputs=lamT)
+    assert np.allclose(g2.cpu().numpy(), grad, rtol=1e-13, atol=0)
+
+
+def test_channel_n5_16_gradient_vs_finite_differences():
+    """Config: N = 5, 16^3 stretched channel, 50 steps, FP64; 20 seeded directions,
+    eps = 1e-6 (relative to the per-variable RMS of U0)."""
+    need_gpu()
+    wl = workloads.WORKLOADS["channel_n5_16x16x16"]
+    U, dt = state(wl)
+    S = dgsem.solver_for(wl, with_adjoint=True)
+    Ud = to_dev(U)
+    J0, grad = kinetic_energy_gradient(S, Ud, dt, wl.nsteps, checkpoint_every=10)
+    say("J", J0.item())
+    eps = 1e-6
+    worst = 0.0
+    for r in range(20):
+        d = workloads.fd_direction(U, r)
+        dd = to_dev(d)
+        Jp = _J(S, Ud + eps * dd, dt, wl.nsteps)
+        Jm = _J(S, Ud - eps * dd, dt, wl.nsteps)
+        fd = (Jp - Jm) / (2 * eps)
+        ad = float((grad * dd).sum().item())
+        rel = abs(fd - ad) / max(abs(ad), 1e-300)
+        worst = max(worst, rel)
+        say(f"dir {r:2d}: adjoint {ad:+.12e}  fd {fd:+.12e}  rel {rel:.2e}")
+    assert worst < 1e-5
+
+
+def _J(S, U0, dt, nsteps):
+    S.set_state(U0.contiguous())
+    S.rk_step(dt, nsteps)
+    UT = S.get_state()
+    return S.kinetic_energy(UT).item()
