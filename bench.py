@@ -49,6 +49,7 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=50)
     return ap.parse_args()
 
 
@@ -151,6 +152,75 @@ def run_precision(wl, U, dt, precision, steps, warmup):
     return res, Ud
 
 
+def run_adjoint(steps: int, K: int):
+    """Adjoint/forward time ratio on the N=5, 48x32x48 stretched channel:
+    mixed-precision forward RK rollout, then the checkpointed FP64 adjoint of
+    the final kinetic energy (forward with checkpoints + segment recompute +
+    reverse steps) against the plain forward of the same steps."""
+    import torch
+
+    from paper_2606_18927_amd import dgsem, workloads
+    from paper_2606_18927_amd.autograd import kinetic_energy_gradient
+
+    wl = workloads.WORKLOADS["channel_n5_48x32x48"]
+    xi, _ = dgsem.lgl(wl.N)
+    U, dt = workloads.make_state(wl, xi)
+    S = dgsem.solver_for(wl, with_adjoint=True)
+    Ud = torch.as_tensor(U.reshape(-1)).cuda()
+    S.set_state(Ud)
+    S.rk_step(dt, 2)
+    S.sync()
+    ev = lambda: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))  # noqa: E731
+    a, b = ev()
+    S.set_state(Ud)
+    a.record(S.stream)
+    S.rk_step(dt, steps)
+    b.record(S.stream)
+    S.sync()
+    torch.cuda.synchronize()
+    t_fwd = a.elapsed_time(b)
+    torch.cuda.reset_peak_memory_stats()
+    base_mem = torch.cuda.memory_allocated()
+    a, b = ev()
+    a.record(S.stream)
+    J, g = kinetic_energy_gradient(S, Ud, dt, steps, checkpoint_every=K)
+    b.record(S.stream)
+    torch.cuda.synchronize()
+    t_adj = a.elapsed_time(b)
+    peak_extra = torch.cuda.max_memory_allocated() - base_mem
+    # kernel level: one right-hand side vs one vector-Jacobian product (FP64)
+    lam = torch.randn_like(Ud)
+    Sf = dgsem.solver_for(wl, with_adjoint=True, precision="fp64")
+    out = Sf.state_like()
+    for _ in range(2):
+        Sf.eval_rhs(Ud, out)
+        Sf.eval_rhs_vjp(Ud, lam, out)
+    reps = 5
+    a, b = ev()
+    a.record(Sf.stream)
+    for _ in range(reps):
+        Sf.eval_rhs(Ud, out)
+    b.record(Sf.stream)
+    c, d = ev()
+    c.record(Sf.stream)
+    for _ in range(reps):
+        Sf.eval_rhs_vjp(Ud, lam, out)
+    d.record(Sf.stream)
+    torch.cuda.synchronize()
+    t_rhs, t_vjp = a.elapsed_time(b) / reps, c.elapsed_time(d) / reps
+    dof = S.n_dof
+    res = {"workload": wl.name, "dof": dof, "steps": steps, "checkpoint_every": K,
+           "forward_precision": "mixed", "adjoint_precision": "fp64",
+           "forward_ms": t_fwd, "forward_ns_per_dof_stage": t_fwd * 1e6 / (dof * steps * 5),
+           "adjoint_total_ms": t_adj, "adjoint_forward_ratio": t_adj / t_fwd,
+           "eval_rhs_fp64_ms": t_rhs, "eval_rhs_vjp_fp64_ms": t_vjp, "vjp_rhs_ratio": t_vjp / t_rhs,
+           "workspace_gb": S.workspace_bytes / 1e9, "adjoint_extra_peak_gb": peak_extra / 1e9,
+           "J": J.item()}
+    del S, Sf
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = _parse()
     if args.gpus != 1:
@@ -178,6 +248,9 @@ def main():
         except dgsem.DgsemError as e:
             mixed = {"error": str(e)}
     adjoint = None
+    if not args.no_adjoint:
+        adjoint = run_adjoint(args.adjoint_steps, 25)
+        print(f"[bench] adjoint/forward {adjoint['adjoint_forward_ratio']:.2f}", file=sys.stderr, flush=True)
     triad = triad_gbs()
     print(f"[bench] triad {triad:.0f} GB/s", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(wl)

@@ -167,3 +167,43 @@ def _J(S, U0, dt, nsteps):
     S.rk_step(dt, nsteps)
     UT = S.get_state()
     return S.kinetic_energy(UT).item()
+
+
+def test_channel_48x32x48_mixed_forward_adjoint_against_fp64():
+    """N = 5, 48x32x48 stretched channel (15.9 M DOF), 500 steps, checkpoint every
+    25: gradient of the final kinetic energy with the mixed-precision forward and
+    the FP64 adjoint, against FP64 forward + FP64 adjoint.  Memory footprint and
+    timings go to gpurun_out/channel_48_adjoint.json."""
+    import json
+    import os
+    import time
+    need_gpu()
+    wl = workloads.WORKLOADS["channel_n5_48x32x48"]
+    U, dt = state(wl)
+    Ud = to_dev(U)
+    res = {"workload": wl.name, "dof": wl.n_dof, "steps": wl.nsteps, "checkpoint_every": wl.checkpoint_every}
+    grads = {}
+    for prec in ("fp64", "mixed"):
+        S = dgsem.solver_for(wl, with_adjoint=True, precision=prec)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        t0 = time.perf_counter()
+        J, g = kinetic_energy_gradient(S, Ud, dt, wl.nsteps, checkpoint_every=wl.checkpoint_every)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        grads[prec] = g.cpu().numpy().reshape(5, -1)
+        res[prec] = {"J": J.item(), "seconds": sec, "workspace_gb": S.workspace_bytes / 1e9,
+                     "rollout_extra_peak_gb": (torch.cuda.max_memory_allocated() - base) / 1e9}
+        say(prec, res[prec])
+        del S, g
+        torch.cuda.empty_cache()
+    e = rel_l2(grads["mixed"], grads["fp64"])
+    names = ["rho", "rho_u", "rho_v", "rho_w", "E"]
+    res["gradient_rel_l2_mixed_vs_fp64"] = dict(zip(names, e.tolist()))
+    res["J_rel_err_mixed_vs_fp64"] = abs(res["mixed"]["J"] - res["fp64"]["J"]) / abs(res["fp64"]["J"])
+    say("gradient rel L2 mixed vs fp64", e, "J rel", res["J_rel_err_mixed_vs_fp64"])
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open(os.path.join("gpurun_out", "channel_48_adjoint.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    assert np.all(e < 1e-3)
