@@ -41,49 +41,55 @@
 namespace dg {
 namespace {
 
-// Line sums of one LDS field q at node (i, j, k) along x, y and z.
-template <int N, typename R>
-__device__ inline void line_sums(const R* sD, const R* q, int i, int j, int k, R& ax, R& ay,
-                                 R& az) {
+// Line sums along direction d of four LDS fields q0..q3 at node (i, j, k);
+// D is read once per line position.
+template <int N, typename R, int d>
+__device__ inline void line_sums4(const R* sD, const R* q0, const R* q1, const R* q2, const R* q3,
+                                  int i, int j, int k, R a[4]) {
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP;
-  ax = ay = az = R(0);
+  const int idx = d == 0 ? i : (d == 1 ? j : k);
+  a[0] = a[1] = a[2] = a[3] = R(0);
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    ax += sD[i * Gm::DS + m] * q[Gm::lds(m, j, k)];
-    ay += sD[j * Gm::DS + m] * q[Gm::lds(i, m, k)];
-    az += sD[k * Gm::DS + m] * q[Gm::lds(i, j, m)];
+    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
+    const R Dm = sD[idx * Gm::DS + m];
+    a[0] += Dm * q0[lm];
+    a[1] += Dm * q1[lm];
+    a[2] += Dm * q2[lm];
+    a[3] += Dm * q3[lm];
   }
 }
 
-// BR1 lifted gradient components g[3 c], g[3 c + 1], g[3 c + 2] of LDS field
-// q (quantity c) at node (i, j, k), with the lifting corrections ssq.
-template <int N, typename R>
-__device__ inline void lifted_gradient(const R* sD, const R* q, int c,
-                                       const R (*ssq)[4][Geo<N>::NF], int i, int j, int k, R sx,
-                                       R sy, R sz, R g[12]) {
-  constexpr int NP = N + 1;
-  R ax, ay, az;
-  line_sums<N, R>(sD, q, i, j, k, ax, ay, az);
-  if (i == 0) ax += ssq[0][c][j + NP * k];
-  if (i == N) ax += ssq[1][c][j + NP * k];
-  if (j == 0) ay += ssq[2][c][i + NP * k];
-  if (j == N) ay += ssq[3][c][i + NP * k];
-  if (k == 0) az += ssq[4][c][i + NP * j];
-  if (k == N) az += ssq[5][c][i + NP * j];
-  g[3 * c + 0] = sx * ax;
-  g[3 * c + 1] = sy * ay;
-  g[3 * c + 2] = sz * az;
-}
-
+// BR1 lifted gradients g[3 q + d] of the four LDS fields q0..q3 at node
+// (i, j, k), with the lifting corrections ssq of the six faces.
 template <int N, typename R>
 __device__ inline void lifted_gradients(const R* sD, const R* q0, const R* q1, const R* q2,
                                         const R* q3, const R (*ssq)[4][Geo<N>::NF], int i, int j,
                                         int k, R sx, R sy, R sz, R g[12]) {
-  lifted_gradient<N, R>(sD, q0, 0, ssq, i, j, k, sx, sy, sz, g);
-  lifted_gradient<N, R>(sD, q1, 1, ssq, i, j, k, sx, sy, sz, g);
-  lifted_gradient<N, R>(sD, q2, 2, ssq, i, j, k, sx, sy, sz, g);
-  lifted_gradient<N, R>(sD, q3, 3, ssq, i, j, k, sx, sy, sz, g);
+  constexpr int NP = N + 1;
+  R a[4];
+  line_sums4<N, R, 0>(sD, q0, q1, q2, q3, i, j, k, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (i == 0) a[c] += ssq[0][c][j + NP * k];
+    if (i == N) a[c] += ssq[1][c][j + NP * k];
+    g[3 * c + 0] = sx * a[c];
+  }
+  line_sums4<N, R, 1>(sD, q0, q1, q2, q3, i, j, k, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (j == 0) a[c] += ssq[2][c][i + NP * k];
+    if (j == N) a[c] += ssq[3][c][i + NP * k];
+    g[3 * c + 1] = sy * a[c];
+  }
+  line_sums4<N, R, 2>(sD, q0, q1, q2, q3, i, j, k, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (k == 0) a[c] += ssq[4][c][i + NP * j];
+    if (k == N) a[c] += ssq[5][c][i + NP * j];
+    g[3 * c + 2] = sz * a[c];
+  }
 }
 
 // Viscous stress and heat flux of gradients g: tau = (t00, t11, t22, t01, t02, t12)
@@ -278,12 +284,41 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 // k_rhs
 // --------------------------------------------------------------------------
 
+// Vector of two R values (one 64- or 128-bit LDS access).
+template <typename R>
+struct V2T;
+template <>
+struct V2T<double> {
+  using type = double2;
+};
+template <>
+struct V2T<float> {
+  using type = float2;
+};
+
+// Kennedy-Gruber flux along d from half values: a, b = ((rho, u), (v, w), (p, e)) / 2,
+// so that {{x}} = a.x + b.x exactly as (x_a + x_b) / 2.
+template <int d, typename R, typename V2>
+__device__ inline void kg_flux_half(const V2 a[3], const V2 b[3], R f[5]) {
+  const R rho = a[0].x + b[0].x;
+  const R u = a[0].y + b[0].y, v = a[1].x + b[1].x, w = a[1].y + b[1].y;
+  const R p = a[2].x + b[2].x, e = a[2].y + b[2].y;
+  const R ud = d == 0 ? u : (d == 1 ? v : w);
+  const R mass = rho * ud;
+  f[0] = mass;
+  f[1] = mass * u;
+  f[2] = mass * v;
+  f[3] = mass * w;
+  f[1 + d] += p;
+  f[4] = mass * e + p * ud;
+}
+
 // Line sums of direction d at node (i, j, k): ac = sum_m D_im f#_KG(own, m),
-// av = sum_m D_im f_v,d(m), du = sum_m D_im u_d,m (mixed-precision add-back).
-template <int N, typename R, int d, bool VISC, bool MIXED>
-__device__ inline void volume_sweep(const R (&own)[6], int i, int j, int k, const R* sD,
-                                    const R (*sp)[Geo<N>::EB], const R (*sfv)[Geo<N>::EB], R ac[5],
-                                    R av[4], R& du) {
+// av = sum_m D_im f_v,d(m), du = sum_m D_im u_d,m / 2 (mixed-precision add-back).
+template <int N, typename R, int d, bool VISC, bool MIXED, typename V2>
+__device__ inline void volume_sweep(const V2 (&own)[3], int i, int j, int k, const R* sD,
+                                    const V2 (*sp)[Geo<N>::EB], const V2 (*sfv)[Geo<N>::EB],
+                                    R ac[5], R av[4], R& du) {
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP;
   const int idx = d == 0 ? i : (d == 1 ? j : k);
@@ -296,18 +331,77 @@ __device__ inline void volume_sweep(const R (&own)[6], int i, int j, int k, cons
   for (int m = 0; m < NP; ++m) {
     const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
     const R Dim = sD[idx * Gm::DS + m];
-    R b[6];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) b[q] = sp[q][lm];
+    const V2 b[3] = {sp[0][lm], sp[1][lm], sp[2][lm]};
     R f[5];
-    kg_flux<d, R>(own, b, f);
+    kg_flux_half<d, R, V2>(own, b, f);
 #pragma unroll
     for (int v = 0; v < 5; ++v) ac[v] += Dim * f[v];
-    if (MIXED) du += Dim * b[1 + d];
+    if (MIXED) du += Dim * (d == 0 ? b[0].y : (d == 1 ? b[1].x : b[1].y));
     if (VISC) {
-#pragma unroll
-      for (int c = 0; c < 4; ++c) av[c] += Dim * sfv[c][lm];
+      const V2 f01 = sfv[0][lm], f23 = sfv[1][lm];
+      av[0] += Dim * f01.x;
+      av[1] += Dim * f01.y;
+      av[2] += Dim * f23.x;
+      av[3] += Dim * f23.y;
     }
+  }
+}
+
+// Line sums along direction d of the half values of u, v, w (packed LDS
+// fields) and of T at node (i, j, k); D is read once per line position.
+template <int N, typename R, int d, typename V2>
+__device__ inline void line_sums_half(const R* sD, const V2 (*sp)[Geo<N>::EB], const R* sT, int i,
+                                      int j, int k, R a[4]) {
+  using Gm = Geo<N>;
+  constexpr int NP = Gm::NP;
+  const int idx = d == 0 ? i : (d == 1 ? j : k);
+  a[0] = a[1] = a[2] = a[3] = R(0);
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
+    const R Dm = sD[idx * Gm::DS + m];
+    const V2 ru = sp[0][lm], vw = sp[1][lm];
+    a[0] += Dm * ru.y;
+    a[1] += Dm * vw.x;
+    a[2] += Dm * vw.y;
+    a[3] += Dm * sT[lm];
+  }
+}
+
+// BR1 lifted gradients g[3 q + d] at node (i, j, k) from the half values of
+// u, v, w and from T, with the lifting corrections ssq of the six faces.
+template <int N, typename R, typename V2>
+__device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[Geo<N>::EB],
+                                             const R* sT, const R (*ssq)[4][Geo<N>::NF], int i,
+                                             int j, int k, R sx, R sy, R sz, R g[12]) {
+  constexpr int NP = N + 1;
+  R a[4];
+  // x
+  line_sums_half<N, R, 0, V2>(sD, sp, sT, i, j, k, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    R t = c < 3 ? R(2) * a[c] : a[c];  // half values: twice the line sum (exact)
+    if (i == 0) t += ssq[0][c][j + NP * k];
+    if (i == N) t += ssq[1][c][j + NP * k];
+    g[3 * c + 0] = sx * t;
+  }
+  // y
+  line_sums_half<N, R, 1, V2>(sD, sp, sT, i, j, k, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    R t = c < 3 ? R(2) * a[c] : a[c];
+    if (j == 0) t += ssq[2][c][i + NP * k];
+    if (j == N) t += ssq[3][c][i + NP * k];
+    g[3 * c + 1] = sy * t;
+  }
+  // z
+  line_sums_half<N, R, 2, V2>(sD, sp, sT, i, j, k, a);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    R t = c < 3 ? R(2) * a[c] : a[c];
+    if (k == 0) t += ssq[4][c][i + NP * j];
+    if (k == N) t += ssq[5][c][i + NP * j];
+    g[3 * c + 2] = sz * t;
   }
 }
 
@@ -380,9 +474,10 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB;
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
   constexpr bool MIXED = sizeof(R) == 4;
+  using V2 = typename V2T<R>::type;
   __shared__ R sD[NP * Gm::DS];
-  __shared__ R sp[EPB][6][EB];      // rho, u, v, w, p - p_ref, e - e_ref
-  __shared__ R sfv[EPB][4][EB];     // f_v,d of the current direction; [0] = T - T_ref in P1-P2
+  __shared__ V2 sp[EPB][3][EB];     // halves of (rho, u), (v, w), (p - p_ref, e - e_ref)
+  __shared__ V2 sfv[EPB][2][EB];    // f_v,d of the current direction; T - T_ref in P1-P2
   __shared__ R sX[EPB][6][5][NF];   // lifting corrections (P1-P2), then surface corrections
   __shared__ R sfvf[EPB][6][4][NF]; // own f_v,d on the face nodes
   R(*ssq)[6][4][NF] = reinterpret_cast<R(*)[6][4][NF]>(&sX[0][0][0][0]);
@@ -425,9 +520,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   }
 
   // ---- P1: node lanes --------------------------------------------------
-  R own[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+  V2 own[3];
+  own[0].x = own[0].y = own[1].x = own[1].y = own[2].x = own[2].y = R(0);
+  R uo = R(0), vo = R(0), wo = R(0);  // own velocity (full values)
   double p_ref = 0.0, e_ref = 0.0;
   int ex = ex0, ey = ey0, ez = ez0;
+  R* sT = reinterpret_cast<R*>(&sfv[le][0][0]);
   if (active) {
     if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
     double u0[5];
@@ -436,15 +534,18 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
     double T_ref;
     element_ref<R>(U, stride, e, NN, ph, p_ref, e_ref, T_ref);
-    own[0] = static_cast<R>(P.rho);
-    own[1] = static_cast<R>(P.u);
-    own[2] = static_cast<R>(P.v);
-    own[3] = static_cast<R>(P.w);
-    own[4] = static_cast<R>(P.p - p_ref);
-    own[5] = static_cast<R>(P.e - e_ref);
+    uo = static_cast<R>(P.u);
+    vo = static_cast<R>(P.v);
+    wo = static_cast<R>(P.w);
+    own[0].x = static_cast<R>(0.5 * P.rho);
+    own[0].y = static_cast<R>(0.5 * P.u);
+    own[1].x = static_cast<R>(0.5 * P.v);
+    own[1].y = static_cast<R>(0.5 * P.w);
+    own[2].x = static_cast<R>(0.5 * (P.p - p_ref));
+    own[2].y = static_cast<R>(0.5 * (P.e - e_ref));
 #pragma unroll
-    for (int q = 0; q < 6; ++q) sp[le][q][l] = own[q];
-    if (VISC) sfv[le][0][l] = static_cast<R>(P.T - T_ref);
+    for (int q = 0; q < 3; ++q) sp[le][q][l] = own[q];
+    if (VISC) sT[l] = static_cast<R>(P.T - T_ref);
   }
   __syncthreads();
 
@@ -456,9 +557,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   if (VISC) {
     if (active) {
       R g[12];
-      lifted_gradients<N, R>(sD, sp[le][1], sp[le][2], sp[le][3], sfv[le][0], ssq[le], i, j, k,
-                             static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
-                             static_cast<R>(mesh.s[2][ez]), g);
+      lifted_gradients_half<N, R, V2>(sD, sp[le], sT, ssq[le], i, j, k,
+                                      static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
+                                      static_cast<R>(mesh.s[2][ez]), g);
       stress<R>(g, mu, kappa, tau, qT);
     }
     __syncthreads();
@@ -473,8 +574,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     const int ab = D == 0 ? j + NP * k : (D == 1 ? i + NP * k : i + NP * j);                \
     if (VISC && active) {                                                                   \
       R fv[4];                                                                              \
-      viscous_flux_tau<D, R>(own[1], own[2], own[3], tau, qT, fv);                          \
-      _Pragma("unroll") for (int c = 0; c < 4; ++c) sfv[le][c][l] = fv[c];                  \
+      viscous_flux_tau<D, R>(uo, vo, wo, tau, qT, fv);                                      \
+      sfv[le][0][l] = V2{fv[0], fv[1]};                                                     \
+      sfv[le][1][l] = V2{fv[2], fv[3]};                                                     \
       if (idx == 0)                                                                         \
         _Pragma("unroll") for (int c = 0; c < 4; ++c) sfvf[le][2 * D][c][ab] = fv[c];       \
       if (idx == N)                                                                         \
@@ -483,14 +585,14 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     __syncthreads();                                                                        \
     if (active) {                                                                           \
       R ac[5], av[4], du;                                                                   \
-      volume_sweep<N, R, D, VISC, MIXED>(own, i, j, k, sD, sp[le], sfv[le], ac, av, du);    \
+      volume_sweep<N, R, D, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sfv[le], ac, av, du); \
       const double sd = mesh.s[D][D == 0 ? ex : (D == 1 ? ey : ez)];                         \
       ut[0] -= sd * static_cast<double>(R(2) * ac[0]);                                      \
       _Pragma("unroll") for (int c = 0; c < 4; ++c)                                         \
           ut[1 + c] -= sd * static_cast<double>(R(2) * ac[1 + c] - av[c]);                  \
       if (MIXED)                                                                            \
-        ut[4] -= sd * (2.0 * e_ref * static_cast<double>(ac[0]) +                           \
-                       p_ref * static_cast<double>(du));                                    \
+        ut[4] -= sd * 2.0 * (e_ref * static_cast<double>(ac[0]) +                           \
+                             p_ref * static_cast<double>(du));                              \
     }                                                                                       \
     __syncthreads();                                                                        \
   }
