@@ -202,20 +202,28 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   int ex0 = 0, ey0 = 0, ez0 = 0;
   elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
 
-  // P1: face lanes form the BR1 lifting corrections (FP64), node lanes stage
-  // (u, v, w, T - T_ref) in LDS
-  if (tid < n_face_tasks<N>()) {
+  // P1: node lanes stage (u, v, w, T - T_ref) in LDS; face lanes fetch the
+  // neighbour state and form the BR1 lifting corrections in FP64 (after the
+  // barrier with the own values from LDS in FP64 mode; mixed precision
+  // recovers the own FP64 values from U)
+  constexpr bool MIXED = sizeof(R) == 4;
+  const bool face_lane = tid < n_face_tasks<N>();
+  const bool face_ok = face_lane && (EPB == 1 ? e0 : e0 + FaceTask<N>(face_lane ? tid : 0).le) < nE;
+  double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  bool fwall = true;
+  if (face_ok) {
     const FaceTask<N> ft(tid);
     const long long te = EPB == 1 ? e0 : e0 + ft.le;
-    if (te < nE) {
-      int ex = ex0, ey = ey0, ez = ez0;
-      if (EPB > 1) elem_coords(te, mesh, ex, ey, ez);
-      const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
-      double so[5], sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+    int ex = ex0, ey = ey0, ez = ez0;
+    if (EPB > 1) elem_coords(te, mesh, ex, ey, ez);
+    const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
+    fwall = nb < 0;
+    if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
+    if (MIXED) {
+      double so[5];
       load_state(U, stride, te * NN + ft.own_node(), so);
-      if (nb >= 0) load_state(U, stride, nb * NN + ft.nb_node(), sn);
       double corr[4];
-      lifting_correction(primitives(so, ph), primitives(sn, ph), nb < 0, mesh.T_wall, ft.up,
+      lifting_correction(primitives(so, ph), primitives(sn, ph), fwall, mesh.T_wall, ft.up,
                          basis.inv_w_end, corr);
 #pragma unroll
       for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
@@ -240,6 +248,25 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     }
   }
   __syncthreads();
+  if (!MIXED) {
+    if (face_ok) {
+      const FaceTask<N> ft(tid);
+      const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
+      const double qo[4] = {sq[ft.le][0][lo], sq[ft.le][1][lo], sq[ft.le][2][lo], sq[ft.le][3][lo]};
+      double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+      if (!fwall) {
+        const Prim Pn = primitives(sn, ph);
+        qs[0] = 0.5 * (qo[0] + Pn.u);
+        qs[1] = 0.5 * (qo[1] + Pn.v);
+        qs[2] = 0.5 * (qo[2] + Pn.w);
+        qs[3] = 0.5 * (qo[3] + Pn.T);
+      }
+      const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>((qs[c] - qo[c]) * sc);
+    }
+    __syncthreads();
+  }
 
   // P2: one lane per face node: lifted gradients and f_v,d of each face the
   // node lies on
@@ -500,22 +527,31 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
 
   // ---- P1: face lanes --------------------------------------------------
+  // FP64: the face lanes only fetch the neighbour's state here and form the
+  // lifting corrections after the barrier, with the own values from LDS.
+  // Mixed precision: the corrections need FP64 own values, recovered from U.
   const bool face_lane = tid < n_face_tasks<N>();
-  if (face_lane && e0 + FaceTask<N>(tid).le < nE) {
+  const bool face_ok = face_lane && e0 + FaceTask<N>(face_lane ? tid : 0).le < nE;
+  double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  bool fwall = true;
+  if (face_ok) {
     const FaceTask<N> ft(tid);
     const long long te = EPB == 1 ? e0 : e0 + ft.le;
     int fx = ex0, fy = ey0, fz = ez0;
     if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
     const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
+    fwall = nb < 0;
     if (VISC) {
-      double so[5], sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-      load_state(U, stride, te * NN + ft.own_node(), so);
-      if (nb >= 0) load_state(U, stride, nb * NN + ft.nb_node(), sn);
-      double corr[4];
-      lifting_correction(primitives(so, ph), primitives(sn, ph), nb < 0, mesh.T_wall, ft.up,
-                         basis.inv_w_end, corr);
+      if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
+      if (MIXED) {
+        double so[5];
+        load_state(U, stride, te * NN + ft.own_node(), so);
+        double corr[4];
+        lifting_correction(primitives(so, ph), primitives(sn, ph), fwall, mesh.T_wall, ft.up,
+                           basis.inv_w_end, corr);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
+        for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
+      }
     }
   }
 
@@ -526,9 +562,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   double p_ref = 0.0, e_ref = 0.0;
   int ex = ex0, ey = ey0, ez = ez0;
   R* sT = reinterpret_cast<R*>(&sfv[le][0][0]);
+  // the own state stays in registers for the RK update: re-reading it at the
+  // end of the workgroup's life would miss in L2 and cost another HBM pass
+  double u0[5] = {0, 0, 0, 0, 0};
   if (active) {
     if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
-    double u0[5];
     load_state(U, stride, e * NN + node, u0);
     const Prim P = primitives(u0, ph);
     if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
@@ -548,6 +586,28 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     if (VISC) sT[l] = static_cast<R>(P.T - T_ref);
   }
   __syncthreads();
+
+  if (VISC && !MIXED) {
+    if (face_ok) {
+      const FaceTask<N> ft(tid);
+      const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
+      const R* sTf = reinterpret_cast<const R*>(&sfv[ft.le][0][0]);
+      const V2 ru = sp[ft.le][0][lo], vw = sp[ft.le][1][lo];
+      const double qo[4] = {2.0 * ru.y, 2.0 * vw.x, 2.0 * vw.y, sTf[lo]};
+      double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+      if (!fwall) {
+        const Prim Pn = primitives(sn, ph);
+        qs[0] = 0.5 * (qo[0] + Pn.u);
+        qs[1] = 0.5 * (qo[1] + Pn.v);
+        qs[2] = 0.5 * (qo[2] + Pn.w);
+        qs[3] = 0.5 * (qo[3] + Pn.T);
+      }
+      const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>((qs[c] - qo[c]) * sc);
+    }
+    __syncthreads();
+  }
 
   // ---- P2: lifted gradients --------------------------------------------
   R tau[6], qT[3];
@@ -653,7 +713,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int v = 0; v < 5; ++v) {
         const double gv = (st.read_G ? st.A * out[v * stride + idx] : 0.0) + st.dt * ut[v];
         out[v * stride + idx] = gv;
-        U_out[v * stride + idx] = U[v * stride + idx] + st.B * gv;
+        U_out[v * stride + idx] = u0[v] + st.B * gv;
       }
     } else {
 #pragma unroll
