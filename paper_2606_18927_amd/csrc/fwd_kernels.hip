@@ -434,17 +434,15 @@ __device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[Geo<N>:
 
 // Surface correction of one face task (FP64):
 //   ((F*_c - F*_v) - (f_c - f_v)(own)) (+-1/w_end),
-// accumulated term by term to keep few values live.  so, sn: own and
-// neighbour conservative states at the face node; fvo, fvn: their normal
-// viscous fluxes.
+// accumulated term by term to keep few values live.  A = own (rho, u, v, w, p, e);
+// so, sn: own and neighbour conservative states at the face node; fvo, fvn:
+// their normal viscous fluxes.
 template <int d>
-__device__ inline void surface_correction(const double so[5], const double sn[5], bool wall,
-                                          bool up, const double fvo[4], const double fvn[4],
-                                          const DevPhys& ph, double inv_w, double corr[5]) {
-  const double iro = 1.0 / so[0];
-  const double a[6] = {so[0], so[1] * iro, so[2] * iro, so[3] * iro, 0.0, so[4] * iro};
-  const double po = ph.gm1 * (so[4] - 0.5 * so[0] * (a[1] * a[1] + a[2] * a[2] + a[3] * a[3]));
-  double A[6] = {a[0], a[1], a[2], a[3], po, a[5]};
+__device__ inline void surface_correction(const double A[6], const double so[5], const double sn[5],
+                                          bool wall, bool up, const double fvo[4],
+                                          const double fvn[4], const DevPhys& ph, double inv_w,
+                                          double corr[5]) {
+  const double po = A[4];
   // minus the own physical flux (f_c - f_v)
   {
     const double ud = A[1 + d];
@@ -474,7 +472,7 @@ __device__ inline void surface_correction(const double so[5], const double sn[5]
 #pragma unroll
     for (int v = 0; v < 5; ++v) corr[v] += F[v];
     if (!ph.central) {
-      const double cu = fabs(A[1 + d]) + sqrt(ph.gamma * po * iro);
+      const double cu = fabs(A[1 + d]) + sqrt(ph.gamma * po / A[0]);
       const double cn = fabs(B[1 + d]) + sqrt(ph.gamma * pn * irn);
       const double lam = cu >= cn ? cu : cn;
       // -lambda/2 (U_R - U_L), L = the lower side of the face
@@ -505,8 +503,14 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   __shared__ R sD[NP * Gm::DS];
   __shared__ V2 sp[EPB][3][EB];     // halves of (rho, u), (v, w), (p - p_ref, e - e_ref)
   __shared__ V2 sfv[EPB][2][EB];    // f_v,d of the current direction; T - T_ref in P1-P2
-  __shared__ R sX[EPB][6][5][NF];   // lifting corrections (P1-P2), then surface corrections
-  __shared__ R sfvf[EPB][6][4][NF]; // own f_v,d on the face nodes
+  // sX: lifting corrections (P1-P2, as ssq), own f_v,d of the face nodes in
+  // components 0..3 (P3-P4), surface corrections (P4-P5).  In P4 every face
+  // lane reads and then overwrites only its own (face, node) entries.
+  __shared__ R sX[EPB][6][5][NF];
+  // neighbour conservative state at the face nodes (P1-P4); the own one too in
+  // mixed precision, where the FP32 halves in sp cannot give it back in FP64
+  __shared__ double sN[EPB][6][5][NF];
+  __shared__ double sO[MIXED ? EPB : 1][6][5][MIXED ? NF : 1];
   R(*ssq)[6][4][NF] = reinterpret_cast<R(*)[6][4][NF]>(&sX[0][0][0][0]);
 
   const int tid = threadIdx.x;
@@ -541,11 +545,13 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
     const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
     fwall = nb < 0;
-    if (VISC) {
-      if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
-      if (MIXED) {
-        double so[5];
-        load_state(U, stride, te * NN + ft.own_node(), so);
+    if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
+    if (MIXED) {
+      double so[5];
+      load_state(U, stride, te * NN + ft.own_node(), so);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) sO[ft.le][ft.f][v][ft.ab] = so[v];
+      if (VISC) {
         double corr[4];
         lifting_correction(primitives(so, ph), primitives(sn, ph), fwall, mesh.T_wall, ft.up,
                            basis.inv_w_end, corr);
@@ -553,6 +559,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
         for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
       }
     }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sN[ft.le][ft.f][v][ft.ab] = sn[v];
   }
 
   // ---- P1: node lanes --------------------------------------------------
@@ -638,9 +646,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       sfv[le][0][l] = V2{fv[0], fv[1]};                                                     \
       sfv[le][1][l] = V2{fv[2], fv[3]};                                                     \
       if (idx == 0)                                                                         \
-        _Pragma("unroll") for (int c = 0; c < 4; ++c) sfvf[le][2 * D][c][ab] = fv[c];       \
+        _Pragma("unroll") for (int c = 0; c < 4; ++c) sX[le][2 * D][c][ab] = fv[c];         \
       if (idx == N)                                                                         \
-        _Pragma("unroll") for (int c = 0; c < 4; ++c) sfvf[le][2 * D + 1][c][ab] = fv[c];   \
+        _Pragma("unroll") for (int c = 0; c < 4; ++c) sX[le][2 * D + 1][c][ab] = fv[c];     \
     }                                                                                       \
     __syncthreads();                                                                        \
     if (active) {                                                                           \
@@ -661,33 +669,55 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   DG_DIRECTION(2)
 #undef DG_DIRECTION
 
+  // G of the RK update is fetched now, so that its latency overlaps P4
+  double gA[5] = {0, 0, 0, 0, 0};
+  if (RK && active && st.read_G) {
+    const long long gi = e * NN + node;
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gA[v] = st.A * out[v * stride + gi];
+  }
+
   // ---- P4: surface corrections (face lanes, FP64) -----------------------
-  if (face_lane && e0 + FaceTask<N>(tid).le < nE) {
+  if (face_ok) {
     const FaceTask<N> ft(tid);
     const long long te = EPB == 1 ? e0 : e0 + ft.le;
     int fx = ex0, fy = ey0, fz = ez0;
     if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
     const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
-    // own and neighbour states at the face node: second reads, served by the
-    // cache (this workgroup read the same lines in P1)
-    const bool wall = nb < 0;
-    double so[5], sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-    load_state(U, stride, te * NN + ft.own_node(), so);
-    if (!wall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
     double fvo[4] = {0, 0, 0, 0}, fvn[4] = {0, 0, 0, 0};
+    if (VISC && !fwall) {
+      const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) fvn[c] = static_cast<double>(src[c * NF]);
+    }
+    double A[6], so[5], sn[5];
+    if (MIXED) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) so[v] = sO[ft.le][ft.f][v][ft.ab];
+      const Prim P = primitives(so, ph);
+      A[0] = P.rho; A[1] = P.u; A[2] = P.v; A[3] = P.w; A[4] = P.p; A[5] = P.e;
+    } else {
+      // FP64: the halves in sp are exact, and p_ref = e_ref = 0
+      const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
+      const V2 a0 = sp[ft.le][0][lo], a1 = sp[ft.le][1][lo], a2 = sp[ft.le][2][lo];
+      A[0] = 2.0 * a0.x; A[1] = 2.0 * a0.y; A[2] = 2.0 * a1.x; A[3] = 2.0 * a1.y;
+      A[4] = 2.0 * a2.x; A[5] = 2.0 * a2.y;
+      so[0] = A[0];
+      so[1] = A[0] * A[1];
+      so[2] = A[0] * A[2];
+      so[3] = A[0] * A[3];
+      so[4] = A[0] * A[5];
+    }
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sn[v] = sN[ft.le][ft.f][v][ft.ab];
     if (VISC) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) fvo[c] = static_cast<double>(sfvf[ft.le][ft.f][c][ft.ab]);
-      if (!wall) {
-        const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) fvn[c] = static_cast<double>(src[c * NF]);
-      }
+      for (int c = 0; c < 4; ++c) fvo[c] = static_cast<double>(sX[ft.le][ft.f][c][ft.ab]);
     }
     double corr[5];
-    if (ft.d == 0) surface_correction<0>(so, sn, wall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
-    if (ft.d == 1) surface_correction<1>(so, sn, wall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
-    if (ft.d == 2) surface_correction<2>(so, sn, wall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    if (ft.d == 0) surface_correction<0>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    if (ft.d == 1) surface_correction<1>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    if (ft.d == 2) surface_correction<2>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
 #pragma unroll
     for (int v = 0; v < 5; ++v) sX[ft.le][ft.f][v][ft.ab] = static_cast<R>(corr[v]);
   }
@@ -711,7 +741,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     if (RK) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const double gv = (st.read_G ? st.A * out[v * stride + idx] : 0.0) + st.dt * ut[v];
+        const double gv = gA[v] + st.dt * ut[v];
         out[v * stride + idx] = gv;
         U_out[v * stride + idx] = u0[v] + st.B * gv;
       }
