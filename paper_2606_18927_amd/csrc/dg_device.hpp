@@ -12,15 +12,17 @@ template <int N>
 struct Cfg;
 template <>
 struct Cfg<3> {
-  static constexpr int EPB = 2, BS = 192;
+  // EPB elements per workgroup of BS lanes; FACE_WAVES: waves per SIMD the
+  // face-flux kernel is register-bounded for
+  static constexpr int EPB = 2, BS = 192, FACE_WAVES = 4;
 };
 template <>
 struct Cfg<5> {
-  static constexpr int EPB = 1, BS = 256;
+  static constexpr int EPB = 1, BS = 256, FACE_WAVES = 8;
 };
 template <>
 struct Cfg<7> {
-  static constexpr int EPB = 1, BS = 512;
+  static constexpr int EPB = 1, BS = 512, FACE_WAVES = 8;
 };
 
 template <int N>
@@ -59,15 +61,26 @@ __device__ inline void elem_coords(long long e, const DevMesh& m, int& ex, int& 
 
 // Face neighbour of element (ex, ey, ez) across its lower (up = false) or
 // upper face normal to d; -1 on a wall.
+// a[d] for a per-lane d from three uniform values held in registers: a
+// per-lane index into the by-value mesh argument (or a select between its
+// fields, which the compiler folds into one) is a dependent memory load.
+__device__ inline int pick3(int a0, int a1, int a2, int d) {
+  a0 = __builtin_amdgcn_readfirstlane(a0);
+  a1 = __builtin_amdgcn_readfirstlane(a1);
+  a2 = __builtin_amdgcn_readfirstlane(a2);
+  return d == 0 ? a0 : (d == 1 ? a1 : a2);
+}
+
 __device__ inline long long neighbour(const DevMesh& m, int ex, int ey, int ez, int d, bool up) {
-  int c[3] = {ex, ey, ez};
-  int v = c[d] + (up ? 1 : -1);
-  if (v < 0 || v >= m.n[d]) {
-    if (m.bc[d] != DG_BC_PERIODIC) return -1;
-    v = v < 0 ? m.n[d] - 1 : 0;
+  const int nd = pick3(m.n[0], m.n[1], m.n[2], d);
+  const int bcd = pick3(m.bc[0], m.bc[1], m.bc[2], d);
+  int v = (d == 0 ? ex : (d == 1 ? ey : ez)) + (up ? 1 : -1);
+  if (v < 0 || v >= nd) {
+    if (bcd != DG_BC_PERIODIC) return -1;
+    v = v < 0 ? nd - 1 : 0;
   }
-  c[d] = v;
-  return static_cast<long long>(c[0] + m.n[0] * (c[1] + m.n[1] * c[2]));
+  const int x = d == 0 ? v : ex, y = d == 1 ? v : ey, z = d == 2 ? v : ez;
+  return static_cast<long long>(x + m.n[0] * (y + m.n[1] * z));
 }
 
 // Node (i, j, k) of face f = 2 d + up with in-face coordinates (a, b):

@@ -132,17 +132,21 @@ __device__ inline void lifting_correction(const Prim& Po, const Prim& Pn, bool w
   for (int c = 0; c < 4; ++c) out[c] = (qs[c] - qo[c]) * sc;
 }
 
+// Per-element reference (p, e, T) of the mixed-precision sweeps: the values at
+// node 0 (state s0), or zero in FP64 and with the subtraction switched off.
 template <typename R>
-__device__ inline void element_ref(const double* U, long long stride, long long e, int NN,
-                                   const DevPhys& ph, double& p_ref, double& e_ref,
-                                   double& T_ref) {
-  if (sizeof(R) == sizeof(double) || !ph.mixed_ref) {
+__device__ inline bool uses_ref(const DevPhys& ph) {
+  return sizeof(R) == sizeof(float) && ph.mixed_ref;
+}
+
+template <typename R>
+__device__ inline void element_ref(const double s0[5], const DevPhys& ph, double& p_ref,
+                                   double& e_ref, double& T_ref) {
+  if (!uses_ref<R>(ph)) {
     p_ref = e_ref = T_ref = 0.0;
     return;
   }
-  double s[5];
-  load_state(U, stride, e * NN, s);
-  const Prim P = primitives(s, ph);
+  const Prim P = primitives(s0, ph);
   p_ref = P.p;
   e_ref = P.e;
   T_ref = P.T;
@@ -183,7 +187,7 @@ __host__ __device__ constexpr int n_face_nodes() {
 }
 
 template <int N, typename R>
-__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_face_flux(
+__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<N>::FACE_WAVES))) void k_face_flux(
     const double* __restrict__ U, R* __restrict__ ffv, DevMesh mesh, DevPhys ph, DevBasis basis) {
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB;
@@ -198,7 +202,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   const long long nE = mesh.nE;
   const long long stride = nE * NN;
   const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
-  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * Gm::DS + t % NP] = static_cast<R>(basis.D[t]);
+  // D is fetched with the first loads and written to LDS before the first
+  // barrier, so its latency is not paid on its own
+  static_assert(NP * NP <= BS, "one lane per entry of D");
+  double dval = 0.0;
+  if (tid < NP * NP) dval = basis.D[tid];
   int ex0 = 0, ey0 = 0, ez0 = 0;
   elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
 
@@ -209,6 +217,17 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   constexpr bool MIXED = sizeof(R) == 4;
   const bool face_lane = tid < n_face_tasks<N>();
   const bool face_ok = face_lane && (EPB == 1 ? e0 : e0 + FaceTask<N>(face_lane ? tid : 0).le) < nE;
+  // the own state is fetched first, so that it and the neighbour's face node
+  // are in flight together
+  const int nle = EPB == 1 ? 0 : tid / NN;
+  const int node = tid - nle * NN;
+  const long long ne = EPB == 1 ? e0 : e0 + nle;
+  const bool node_ok = (EPB == 1 ? tid < NN : nle < EPB) && ne < nE;
+  double s[5] = {1.0, 0.0, 0.0, 0.0, 1.0}, s0[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  if (node_ok) {
+    load_state(U, stride, ne * NN + node, s);
+    if (uses_ref<R>(ph)) load_state(U, stride, ne * NN, s0);
+  }
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
   bool fwall = true;
   if (face_ok) {
@@ -229,24 +248,18 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
     }
   }
-  {
-    const int le = EPB == 1 ? 0 : tid / NN;
-    const int node = tid - le * NN;
-    const long long e = EPB == 1 ? e0 : e0 + le;
-    if ((EPB == 1 ? tid < NN : le < EPB) && e < nE) {
-      const int i = node % NP, j = (node / NP) % NP, k = node / NF;
-      double s[5];
-      load_state(U, stride, e * NN + node, s);
-      const Prim P = primitives(s, ph);
-      double p_ref, e_ref, T_ref;
-      element_ref<R>(U, stride, e, NN, ph, p_ref, e_ref, T_ref);
-      const int l = Gm::lds(i, j, k);
-      sq[le][0][l] = static_cast<R>(P.u);
-      sq[le][1][l] = static_cast<R>(P.v);
-      sq[le][2][l] = static_cast<R>(P.w);
-      sq[le][3][l] = static_cast<R>(P.T - T_ref);
-    }
+  if (node_ok) {
+    const int i = node % NP, j = (node / NP) % NP, k = node / NF;
+    const Prim P = primitives(s, ph);
+    double p_ref, e_ref, T_ref;
+    element_ref<R>(s0, ph, p_ref, e_ref, T_ref);
+    const int l = Gm::lds(i, j, k);
+    sq[nle][0][l] = static_cast<R>(P.u);
+    sq[nle][1][l] = static_cast<R>(P.v);
+    sq[nle][2][l] = static_cast<R>(P.w);
+    sq[nle][3][l] = static_cast<R>(P.T - T_ref);
   }
+  if (tid < NP * NP) sD[(tid / NP) * Gm::DS + tid % NP] = static_cast<R>(dval);
   __syncthreads();
   if (!MIXED) {
     if (face_ok) {
@@ -517,7 +530,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   const long long nE = mesh.nE;
   const long long stride = nE * NN;
   const long long e0 = static_cast<long long>(xcd_remap(blockIdx.x, gridDim.x)) * EPB;
-  for (int t = tid; t < NP * NP; t += BS) sD[(t / NP) * Gm::DS + t % NP] = static_cast<R>(basis.D[t]);
+  // D is fetched with the first loads and written to LDS before the first
+  // barrier, so its latency is not paid on its own
+  static_assert(NP * NP <= BS, "one lane per entry of D");
+  double dval = 0.0;
+  if (tid < NP * NP) dval = basis.D[tid];
   const R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
 
   // with one element per workgroup the element index is wave-uniform
@@ -534,6 +551,14 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   // FP64: the face lanes only fetch the neighbour's state here and form the
   // lifting corrections after the barrier, with the own values from LDS.
   // Mixed precision: the corrections need FP64 own values, recovered from U.
+  // The own state is fetched first, so that it and the neighbour's face node
+  // are in flight together.  It stays in registers for the RK update:
+  // re-reading it at the end of the workgroup's life would miss in L2.
+  double u0[5] = {0, 0, 0, 0, 0}, s0[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  if (active) {
+    load_state(U, stride, e * NN + node, u0);
+    if (uses_ref<R>(ph)) load_state(U, stride, e * NN, s0);
+  }
   const bool face_lane = tid < n_face_tasks<N>();
   const bool face_ok = face_lane && e0 + FaceTask<N>(face_lane ? tid : 0).le < nE;
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
@@ -570,16 +595,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   double p_ref = 0.0, e_ref = 0.0;
   int ex = ex0, ey = ey0, ez = ez0;
   R* sT = reinterpret_cast<R*>(&sfv[le][0][0]);
-  // the own state stays in registers for the RK update: re-reading it at the
-  // end of the workgroup's life would miss in L2 and cost another HBM pass
-  double u0[5] = {0, 0, 0, 0, 0};
   if (active) {
     if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
-    load_state(U, stride, e * NN + node, u0);
     const Prim P = primitives(u0, ph);
     if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
     double T_ref;
-    element_ref<R>(U, stride, e, NN, ph, p_ref, e_ref, T_ref);
+    element_ref<R>(s0, ph, p_ref, e_ref, T_ref);
     uo = static_cast<R>(P.u);
     vo = static_cast<R>(P.v);
     wo = static_cast<R>(P.w);
@@ -593,6 +614,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     for (int q = 0; q < 3; ++q) sp[le][q][l] = own[q];
     if (VISC) sT[l] = static_cast<R>(P.T - T_ref);
   }
+  if (tid < NP * NP) sD[(tid / NP) * Gm::DS + tid % NP] = static_cast<R>(dval);
   __syncthreads();
 
   if (VISC && !MIXED) {
@@ -669,12 +691,13 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   DG_DIRECTION(2)
 #undef DG_DIRECTION
 
-  // G of the RK update is fetched now, so that its latency overlaps P4
+  // G of the RK update is fetched now and first used in P5, so that its
+  // latency overlaps P4
   double gA[5] = {0, 0, 0, 0, 0};
   if (RK && active && st.read_G) {
     const long long gi = e * NN + node;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) gA[v] = st.A * out[v * stride + gi];
+    for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + gi];
   }
 
   // ---- P4: surface corrections (face lanes, FP64) -----------------------
@@ -741,7 +764,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     if (RK) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
-        const double gv = gA[v] + st.dt * ut[v];
+        const double gv = st.A * gA[v] + st.dt * ut[v];
         out[v * stride + idx] = gv;
         U_out[v * stride + idx] = u0[v] + st.B * gv;
       }
