@@ -336,25 +336,15 @@ struct V2T<float> {
   using type = float2;
 };
 
-// Kennedy-Gruber flux along d from half values: a, b = ((rho, u), (v, w), (p, e)) / 2,
-// so that {{x}} = a.x + b.x exactly as (x_a + x_b) / 2.
-template <int d, typename R, typename V2>
-__device__ inline void kg_flux_half(const V2 a[3], const V2 b[3], R f[5]) {
-  const R rho = a[0].x + b[0].x;
-  const R u = a[0].y + b[0].y, v = a[1].x + b[1].x, w = a[1].y + b[1].y;
-  const R p = a[2].x + b[2].x, e = a[2].y + b[2].y;
-  const R ud = d == 0 ? u : (d == 1 ? v : w);
-  const R mass = rho * ud;
-  f[0] = mass;
-  f[1] = mass * u;
-  f[2] = mass * v;
-  f[3] = mass * w;
-  f[1 + d] += p;
-  f[4] = mass * e + p * ud;
-}
-
 // Line sums of direction d at node (i, j, k): ac = sum_m D_im f#_KG(own, m),
 // av = sum_m D_im f_v,d(m), du = sum_m D_im u_d,m / 2 (mixed-precision add-back).
+// Own and line values are halves: a, b = ((rho, u), (v, w), (p, e)) / 2, so that
+// {{x}} = a.x + b.x exactly as (x_a + x_b) / 2.  The Kennedy-Gruber flux
+//   f# = ({{rho}}{{u_d}}, {{rho}}{{u_d}}{{u}} + {{p}} delta_1d, ...,
+//         {{u_d}} ({{rho}}{{e}} + {{p}}))
+// enters the sums premultiplied by D_im: with s = D_im {{u_d}} and
+// m = s {{rho}}, the five components take m, m {{u}}, m {{v}}, m {{w}}
+// (+ D_im {{p}} in component 1 + d) and s ({{rho}}{{e}} + {{p}}).
 template <int N, typename R, int d, bool VISC, bool MIXED, typename V2>
 __device__ inline void volume_sweep(const V2 (&own)[3], int i, int j, int k, const R* sD,
                                     const V2 (*sp)[Geo<N>::EB], const V2 (*sfv)[Geo<N>::EB],
@@ -371,12 +361,20 @@ __device__ inline void volume_sweep(const V2 (&own)[3], int i, int j, int k, con
   for (int m = 0; m < NP; ++m) {
     const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
     const R Dim = sD[idx * Gm::DS + m];
-    const V2 b[3] = {sp[0][lm], sp[1][lm], sp[2][lm]};
-    R f[5];
-    kg_flux_half<d, R, V2>(own, b, f);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) ac[v] += Dim * f[v];
-    if (MIXED) du += Dim * (d == 0 ? b[0].y : (d == 1 ? b[1].x : b[1].y));
+    const V2 b0 = sp[0][lm], b1 = sp[1][lm], b2 = sp[2][lm];
+    const R rho = own[0].x + b0.x;
+    const R u = own[0].y + b0.y, v = own[1].x + b1.x, w = own[1].y + b1.y;
+    const R p = own[2].x + b2.x, e = own[2].y + b2.y;
+    const R ud = d == 0 ? u : (d == 1 ? v : w);
+    const R s = Dim * ud;
+    const R mm = s * rho;
+    ac[0] += mm;
+    ac[1] += mm * u;
+    ac[2] += mm * v;
+    ac[3] += mm * w;
+    ac[1 + d] += Dim * p;
+    ac[4] += s * (rho * e + p);
+    if (MIXED) du += Dim * (d == 0 ? b0.y : (d == 1 ? b1.x : b1.y));
     if (VISC) {
       const V2 f01 = sfv[0][lm], f23 = sfv[1][lm];
       av[0] += Dim * f01.x;
