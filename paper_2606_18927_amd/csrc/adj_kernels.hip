@@ -179,8 +179,10 @@ __device__ inline double nb_scale(const DevMesh& m, int ex, int ey, int ez, int 
 // --------------------------------------------------------------------------
 // k_vjp_a
 // --------------------------------------------------------------------------
+// Bounded for two waves per SIMD: without the bound the degree-5 kernel takes a
+// few registers over 256 and runs one wave per SIMD.
 template <int N>
-__global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_a(const double* __restrict__ U,
+__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp_a(const double* __restrict__ U,
                                                        const double* __restrict__ grad,
                                                        const double* __restrict__ lam,
                                                        double* __restrict__ gbar,
