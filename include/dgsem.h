@@ -132,6 +132,26 @@ dg_status dg_eval_rhs_vjp(dg_ctx* ctx, const double* U_dev, const double* lam_de
 dg_status dg_rk_step_vjp(dg_ctx* ctx, const double* U_n_dev, double t, double dt,
                          const double* lamU_np1_dev, double* lamU_n_dev);
 
+/* Segment recompute for the checkpointed adjoint (the paper's RK scheme,
+ * Sec. 4, run forward from a checkpoint): starting from U0, advance nsteps
+ * steps of size dt and write the five stage input states U_{n,s} (s = 0..4;
+ * U_{n,0} = U_n) of every step to the caller-owned device buffer stages, step
+ * major: U_{n,s} starts at stages + (5 n + s) 5 n_dof; the buffer holds
+ * 25 nsteps n_dof doubles and must not overlap U0.  The arithmetic is that of
+ * dg_rk_step (the context's precision); afterwards the context's state is
+ * U_nsteps and its RK register is overwritten.  Errors: DG_EINVAL (null
+ * pointers, nsteps < 1, non-finite dt, U0 inside stages), DG_ESTATE (no
+ * workspace).                                                                */
+dg_status dg_rk_record_stages(dg_ctx* ctx, const double* U0_dev, double t, double dt, int nsteps,
+                              double* stages_dev);
+
+/* dg_rk_step_vjp with the step's five stage states read from stages_dev (the
+ * 25 n_dof doubles dg_rk_record_stages wrote for that step) instead of
+ * recomputed: lamU_n = dJ/dU_n from lamU_np1.  Needs a workspace bound
+ * with_adjoint; FP64 arithmetic.                                             */
+dg_status dg_rk_step_vjp_stages(dg_ctx* ctx, const double* stages_dev, double t, double dt,
+                                const double* lamU_np1_dev, double* lamU_n_dev);
+
 /* Volume-averaged kinetic energy J(U) = sum wJ |m|^2/(2 rho) / sum wJ with LGL
  * quadrature, written to J_dev[0] (device double).                           */
 dg_status dg_kinetic_energy(dg_ctx* ctx, const double* U_dev, double* J_dev);

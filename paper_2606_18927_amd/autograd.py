@@ -2,11 +2,15 @@
 
 ``RKRollout.apply(U0, solver, dt, nsteps, checkpoint_every)`` advances U0 by
 ``nsteps`` RK steps with ``dg_rk_step`` and returns U_T.  Its backward pass
-applies ``dg_rk_step_vjp`` step by step in reverse.  States are checkpointed
-every ``checkpoint_every`` steps during the forward pass; the backward pass
-recomputes the states of one segment at a time from its checkpoint, so the
-memory held is (nsteps / K) checkpoints plus K states of one segment, and each
-step's five stage states live only inside ``dg_rk_step_vjp``.
+goes back step by step with the RK step's vector-Jacobian product.  States
+are checkpointed every ``checkpoint_every`` (K) steps during the forward pass;
+the backward pass recomputes one segment at a time from its checkpoint.  By
+default (``record_stages``) the recompute writes the five stage states of every
+step of the segment (``dg_rk_record_stages``, 25 n_dof doubles per step) and
+the reverse steps read them (``dg_rk_step_vjp_stages``): one forward pass per
+segment, memory (nsteps / K) checkpoints + 5 K states.  Without it the segment
+keeps its K step states and ``dg_rk_step_vjp`` recomputes each step's stages:
+K states, one more forward pass.
 
 ``kinetic_energy_gradient`` is the flow functional used for the adjoint: the
 volume-averaged kinetic energy of U_T and its gradient with respect to the
@@ -39,19 +43,30 @@ def _forward_states(solver: Solver, U0: torch.Tensor, dt: float, nsteps: int, K:
 
 
 def _backward_states(solver: Solver, ckpts: dict, dt: float, nsteps: int, K: int,
-                     lam_T: torch.Tensor) -> torch.Tensor:
+                     lam_T: torch.Tensor, record_stages: bool = True) -> torch.Tensor:
     lam = lam_T.detach().clone().contiguous()
+    spare = torch.empty_like(lam)
     starts = sorted(ckpts)
+    buf = None
     for s0 in reversed(starts):
         s1 = min(s0 + K, nsteps)
-        # recompute the states of the segment [s0, s1)
+        if record_stages:
+            if buf is None:
+                buf = torch.empty((K, 5, 5 * solver.n_dof), dtype=torch.float64, device=lam.device)
+            stages = solver.rk_record_stages(ckpts[s0], dt, s1 - s0, out=buf)
+            for n in range(s1 - 1, s0 - 1, -1):
+                solver.rk_step_vjp_stages(stages[n - s0], dt, lam, out=spare)
+                lam, spare = spare, lam
+            continue
+        # recompute the step states of the segment [s0, s1)
         states = [ckpts[s0]]
         solver.set_state(ckpts[s0])
         for _ in range(s0 + 1, s1):
             solver.rk_step(dt, 1)
             states.append(solver.get_state())
         for n in range(s1 - 1, s0 - 1, -1):
-            lam = solver.rk_step_vjp(states[n - s0], dt, lam)
+            solver.rk_step_vjp(states[n - s0], dt, lam, out=spare)
+            lam, spare = spare, lam
         del states
     solver.sync()
     return lam
@@ -59,29 +74,32 @@ def _backward_states(solver: Solver, ckpts: dict, dt: float, nsteps: int, K: int
 
 class RKRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, solver, dt, nsteps, checkpoint_every):
+    def forward(ctx, U0, solver, dt, nsteps, checkpoint_every, record_stages=True):
         K = max(1, int(checkpoint_every) if checkpoint_every else nsteps)
         UT, ckpts = _forward_states(solver, U0.contiguous(), dt, nsteps, K)
         ctx.solver, ctx.dt, ctx.nsteps, ctx.K, ctx.ckpts = solver, dt, nsteps, K, ckpts
+        ctx.record_stages = bool(record_stages)
         return UT
 
     @staticmethod
     def backward(ctx, gUT):
-        lam0 = _backward_states(ctx.solver, ctx.ckpts, ctx.dt, ctx.nsteps, ctx.K, gUT)
+        lam0 = _backward_states(ctx.solver, ctx.ckpts, ctx.dt, ctx.nsteps, ctx.K, gUT,
+                                ctx.record_stages)
         ctx.ckpts = None
-        return lam0, None, None, None, None
+        return lam0, None, None, None, None, None
 
 
-def rollout(U0: torch.Tensor, solver: Solver, dt: float, nsteps: int, checkpoint_every: int = 0):
-    return RKRollout.apply(U0, solver, dt, nsteps, checkpoint_every)
+def rollout(U0: torch.Tensor, solver: Solver, dt: float, nsteps: int, checkpoint_every: int = 0,
+            record_stages: bool = True):
+    return RKRollout.apply(U0, solver, dt, nsteps, checkpoint_every, record_stages)
 
 
 def kinetic_energy_gradient(solver: Solver, U0: torch.Tensor, dt: float, nsteps: int,
-                            checkpoint_every: int = 0):
+                            checkpoint_every: int = 0, record_stages: bool = True):
     """(J(U_T), dJ/dU0) for the volume-averaged kinetic energy J after nsteps."""
     K = max(1, checkpoint_every or nsteps)
     UT, ckpts = _forward_states(solver, U0.contiguous(), dt, nsteps, K)
     J = solver.kinetic_energy(UT)
     lam_T = solver.kinetic_energy_grad(UT)
-    lam0 = _backward_states(solver, ckpts, dt, nsteps, K, lam_T)
+    lam0 = _backward_states(solver, ckpts, dt, nsteps, K, lam_T, record_stages)
     return J, lam0

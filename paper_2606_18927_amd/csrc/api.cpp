@@ -152,6 +152,69 @@ dg_status eval_rhs_into(dg_ctx* c, const double* U, double* Ut) {
   return st;
 }
 
+// The five stage inputs of one RK step from `in` (stage 0): stage s + 1 is
+// written to stage_out(s) for s < 4 and the step's result to stage_out(4).
+template <typename Out>
+dg_status forward_stages(dg_ctx* c, const double* in, double dt, Out stage_out) {
+  const dg::DevMesh m = dev_mesh(c);
+  const dg::DevPhys p = dev_phys(c);
+  const dg::DevBasis b = dev_basis(c);
+  dg_status st = DG_OK;
+  const double* cur = in;
+  for (int s = 0; s < 5; ++s) {
+    if (c->phys.viscous &&
+        (st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, cur, c->ffv, c->stream),
+                        "face flux kernel")) != DG_OK)
+      return st;
+    const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
+    double* out = stage_out(s);
+    if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, cur, c->ffv, c->G, out,
+                                               stage, c->dstatus, c->stream),
+                        "rk stage kernel")) != DG_OK)
+      return st;
+    cur = out;
+  }
+  return DG_OK;
+}
+
+// Reverse sweep of one RK step over its five stage inputs stage_in(s):
+// cot_s = A_{s+1} cot_{s+1} + B_s lamU;  lamU += dt (dL/dU(U_s))^T cot_s.
+template <typename In>
+dg_status reverse_stages(dg_ctx* c, In stage_in, double dt, const double* lam_np1, double* lam_n) {
+  const dg::DevMesh m = dev_mesh(c);
+  const dg::DevPhys p = dev_phys(c);
+  const dg::DevBasis b = dev_basis(c);
+  const size_t bytes = static_cast<size_t>(5 * c->n_dof) * sizeof(double);
+  dg_status st = DG_OK;
+  if ((st = hip_check(c, hipMemcpyAsync(c->lamU, lam_np1, bytes, hipMemcpyDeviceToDevice, c->stream),
+                      "lam copy")) != DG_OK)
+    return st;
+  if ((st = hip_check(c, hipMemsetAsync(c->lamG, 0, bytes, c->stream), "clear lamG")) != DG_OK) return st;
+  for (int s = 4; s >= 0; --s) {
+    const double a_next = s < 4 ? kRkA[s + 1] : 0.0;
+    if ((st = hip_check(c, dg::launch_axpby(c->lamG, c->lamU, a_next, kRkB[s], 5 * c->n_dof, c->stream),
+                        "axpby kernel")) != DG_OK)
+      return st;
+    if (c->phys.viscous &&
+        (st = hip_check(c, dg::launch_lift(c->N, m, p, b, stage_in(s), c->agrad, c->stream),
+                        "lift kernel")) != DG_OK)
+      return st;
+    if ((st = hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, stage_in(s), c->agrad, c->lamG, c->gbar,
+                                              c->ubar, c->lamU, true, dt, c->stream),
+                        "vjp kernels")) != DG_OK)
+      return st;
+  }
+  return hip_check(c, hipMemcpyAsync(lam_n, c->lamU, bytes, hipMemcpyDeviceToDevice, c->stream),
+                   "lam copy");
+}
+
+dg_status need_adjoint(dg_ctx* c) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
+  return DG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -373,13 +436,9 @@ dg_status dg_eval_rhs_vjp(dg_ctx* c, const double* U, const double* lam, double*
 
 dg_status dg_rk_step_vjp(dg_ctx* c, const double* U_n, double /*t*/, double dt, const double* lam_np1,
                          double* lam_n) {
-  dg_status st = need_bound(c);
+  dg_status st = need_adjoint(c);
   if (st != DG_OK) return st;
-  if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
   if (!U_n || !lam_np1 || !lam_n || !std::isfinite(dt)) return fail(c, DG_EINVAL, "bad arguments");
-  const dg::DevMesh m = dev_mesh(c);
-  const dg::DevPhys p = dev_phys(c);
-  const dg::DevBasis b = dev_basis(c);
   const long long n5 = 5 * c->n_dof;
   const size_t bytes = n5 * sizeof(double);
   auto stage_state = [&](int s) { return c->stages + static_cast<size_t>(s) * n5; };
@@ -387,40 +446,44 @@ dg_status dg_rk_step_vjp(dg_ctx* c, const double* U_n, double /*t*/, double dt, 
   if ((st = hip_check(c, hipMemcpyAsync(stage_state(0), U_n, bytes, hipMemcpyDeviceToDevice, c->stream),
                       "stage copy")) != DG_OK)
     return st;
-  for (int s = 0; s < 5; ++s) {
-    if (c->phys.viscous &&
-        (st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, stage_state(s), c->ffv,
-                                                c->stream),
-                        "face flux kernel")) != DG_OK)
-      return st;
-    const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
-    double* out = s < 4 ? stage_state(s + 1) : c->tmp;
-    if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, stage_state(s), c->ffv,
-                                               c->G, out, stage, c->dstatus, c->stream),
-                        "rk stage kernel")) != DG_OK)
-      return st;
-  }
-  // reverse sweep: cot_s = A_{s+1} cot_{s+1} + B_s lamU;  lamU += dt (dL/dU(U_s))^T cot_s
-  if ((st = hip_check(c, hipMemcpyAsync(c->lamU, lam_np1, bytes, hipMemcpyDeviceToDevice, c->stream),
-                      "lam copy")) != DG_OK)
+  if ((st = forward_stages(c, stage_state(0), dt,
+                           [&](int s) { return s < 4 ? stage_state(s + 1) : c->tmp; })) != DG_OK)
     return st;
-  if ((st = hip_check(c, hipMemsetAsync(c->lamG, 0, bytes, c->stream), "clear lamG")) != DG_OK) return st;
-  for (int s = 4; s >= 0; --s) {
-    const double a_next = s < 4 ? kRkA[s + 1] : 0.0;
-    if ((st = hip_check(c, dg::launch_axpby(c->lamG, c->lamU, a_next, kRkB[s], n5, c->stream),
-                        "axpby kernel")) != DG_OK)
-      return st;
-    if (c->phys.viscous &&
-        (st = hip_check(c, dg::launch_lift(c->N, m, p, b, stage_state(s), c->agrad, c->stream),
-                        "lift kernel")) != DG_OK)
-      return st;
-    if ((st = hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, stage_state(s), c->agrad, c->lamG, c->gbar,
-                                              c->ubar, c->lamU, true, dt, c->stream),
-                        "vjp kernels")) != DG_OK)
+  return reverse_stages(c, [&](int s) -> const double* { return stage_state(s); }, dt, lam_np1, lam_n);
+}
+
+dg_status dg_rk_record_stages(dg_ctx* c, const double* U0, double /*t*/, double dt, int nsteps,
+                              double* stages) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!U0 || !stages || nsteps < 1 || !std::isfinite(dt)) return fail(c, DG_EINVAL, "bad arguments");
+  const size_t n5 = static_cast<size_t>(5 * c->n_dof);
+  if (U0 >= stages && U0 < stages + static_cast<size_t>(nsteps) * 5 * n5)
+    return fail(c, DG_EINVAL, "U0 inside the stage buffer");
+  auto slot = [&](long long q) { return stages + static_cast<size_t>(q) * n5; };
+  if ((st = hip_check(c, hipMemcpyAsync(slot(0), U0, n5 * sizeof(double), hipMemcpyDeviceToDevice,
+                                        c->stream),
+                      "stage copy")) != DG_OK)
+    return st;
+  for (int n = 0; n < nsteps; ++n) {
+    // the last stage of step n writes stage 0 of step n + 1, or the context's
+    // state after the last step
+    double* next = n + 1 < nsteps ? slot(5LL * (n + 1)) : c->U[c->cur ^ 1];
+    if ((st = forward_stages(c, slot(5LL * n), dt,
+                             [&](int s) { return s < 4 ? slot(5LL * n + s + 1) : next; })) != DG_OK)
       return st;
   }
-  return hip_check(c, hipMemcpyAsync(lam_n, c->lamU, bytes, hipMemcpyDeviceToDevice, c->stream),
-                   "lam copy");
+  c->cur ^= 1;
+  return DG_OK;
+}
+
+dg_status dg_rk_step_vjp_stages(dg_ctx* c, const double* stages, double /*t*/, double dt,
+                                const double* lam_np1, double* lam_n) {
+  dg_status st = need_adjoint(c);
+  if (st != DG_OK) return st;
+  if (!stages || !lam_np1 || !lam_n || !std::isfinite(dt)) return fail(c, DG_EINVAL, "bad arguments");
+  const size_t n5 = static_cast<size_t>(5 * c->n_dof);
+  return reverse_stages(c, [&](int s) { return stages + static_cast<size_t>(s) * n5; }, dt, lam_np1, lam_n);
 }
 
 dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double* J) {

@@ -62,6 +62,8 @@ _SIGNATURES = {
     "dg_rk_step": (_I, [_P, _D, _D, _I]),
     "dg_eval_rhs_vjp": (_I, [_P, _P, _P, _P, _D]),
     "dg_rk_step_vjp": (_I, [_P, _P, _D, _D, _P, _P]),
+    "dg_rk_record_stages": (_I, [_P, _P, _D, _D, _I, _P]),
+    "dg_rk_step_vjp_stages": (_I, [_P, _P, _D, _D, _P, _P]),
     "dg_kinetic_energy": (_I, [_P, _P, _P]),
     "dg_kinetic_energy_grad": (_I, [_P, _P, _P]),
     "dg_stream_triad": (_I, [_P, _P, _D, _P, ctypes.c_longlong, _P]),
@@ -221,6 +223,31 @@ class Solver:
         self._check(lib().dg_rk_step_vjp(self._ctx, self._state_ptr(U_n), t, dt,
                                          self._state_ptr(lam_np1, "lam_np1"), self._state_ptr(out, "lam_n")),
                     "dg_rk_step_vjp")
+        return out
+
+    def rk_record_stages(self, U0: torch.Tensor, dt: float, nsteps: int,
+                         out: torch.Tensor | None = None, t: float = 0.0) -> torch.Tensor:
+        """Stage input states of nsteps RK steps from U0, shape (nsteps, 5, 5 n_dof);
+        leaves the context at U_nsteps.  `out` may be a larger buffer: its first
+        nsteps steps are used."""
+        n5 = 5 * self.n_dof
+        if out is None:
+            out = torch.empty((nsteps, 5, n5), dtype=torch.float64, device=self.device)
+        if (not isinstance(out, torch.Tensor) or not out.is_cuda or out.dtype != torch.float64
+                or not out.is_contiguous() or out.numel() < nsteps * 5 * n5):
+            raise ValueError(f"stages: expected a contiguous float64 CUDA tensor of >= {nsteps * 5 * n5} elements")
+        self._check(lib().dg_rk_record_stages(self._ctx, self._state_ptr(U0), t, dt, nsteps, out.data_ptr()),
+                    "dg_rk_record_stages")
+        return out.view(-1)[: nsteps * 5 * n5].view(nsteps, 5, n5)
+
+    def rk_step_vjp_stages(self, stages: torch.Tensor, dt: float, lam_np1: torch.Tensor,
+                           out: torch.Tensor | None = None, t: float = 0.0) -> torch.Tensor:
+        """rk_step_vjp from one step's recorded stage states (5, 5 n_dof)."""
+        out = self.state_like() if out is None else out
+        self._check(lib().dg_rk_step_vjp_stages(self._ctx, _ptr(stages, 25 * self.n_dof, "stages"), t, dt,
+                                                self._state_ptr(lam_np1, "lam_np1"),
+                                                self._state_ptr(out, "lam_n")),
+                    "dg_rk_step_vjp_stages")
         return out
 
     def kinetic_energy(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

@@ -114,6 +114,8 @@ def test_workspace_size_and_state_errors(L):
     # no workspace bound yet: device calls are refused before any HIP call
     assert L.dg_rk_step(ctx, 0.0, 1e-3, 1) == dgsem.DG_ESTATE
     assert L.dg_eval_rhs(ctx, None, None, 0.0) == dgsem.DG_ESTATE
+    assert L.dg_rk_record_stages(ctx, None, 0.0, 1e-3, 1, None) == dgsem.DG_ESTATE
+    assert L.dg_rk_step_vjp_stages(ctx, None, 0.0, 1e-3, None, None) == dgsem.DG_ESTATE
     assert b"workspace" in L.dg_last_error(ctx)
     L.dg_free(ctx)
     # mixed precision halves the face-flux storage

@@ -137,6 +137,42 @@ def test_rollout_kinetic_energy_gradient_against_oracle():
     assert np.allclose(g2.cpu().numpy(), grad, rtol=1e-13, atol=0)
 
 
+def test_recorded_stages_match_rk_step_and_internal_recompute():
+    """dg_rk_record_stages + dg_rk_step_vjp_stages against dg_rk_step and
+    dg_rk_step_vjp: the same kernels on the same inputs, so bit for bit."""
+    need_gpu()
+    wl = custom("channel", 5, (2, 3, 2), seed=workloads.CHANNEL_SEED)
+    U, dt = state(wl)
+    Ud = to_dev(U)
+    for prec in ("fp64", "mixed"):
+        S = dgsem.solver_for(wl, with_adjoint=True, precision=prec)
+        nsteps = 3
+        st = S.rk_record_stages(Ud, dt, nsteps)
+        U_end = S.get_state()
+        S.set_state(Ud)
+        ref_states = [Ud]
+        for _ in range(nsteps):
+            S.rk_step(dt, 1)
+            ref_states.append(S.get_state())
+        S.sync()
+        for n in range(nsteps):
+            assert torch.equal(st[n, 0], ref_states[n]), (prec, n)
+        assert torch.equal(U_end, ref_states[nsteps]), prec
+        rng = np.random.default_rng(41)
+        lam = to_dev(rng.standard_normal(U.shape))
+        for n in range(nsteps):
+            a = S.rk_step_vjp(ref_states[n], dt, lam)
+            b = S.rk_step_vjp_stages(st[n], dt, lam)
+            S.sync()
+            assert torch.equal(a, b), (prec, n)
+        say(prec, "recorded stages: bitwise equal")
+    # the checkpointed gradient is the same with and without recorded stages
+    S = dgsem.solver_for(wl, with_adjoint=True)
+    J1, g1 = kinetic_energy_gradient(S, Ud, dt, 7, checkpoint_every=3, record_stages=True)
+    J2, g2 = kinetic_energy_gradient(S, Ud, dt, 7, checkpoint_every=3, record_stages=False)
+    assert torch.equal(J1, J2) and torch.equal(g1, g2)
+
+
 def test_channel_n5_16_gradient_vs_finite_differences():
     """Config: N = 5, 16^3 stretched channel, 50 steps, FP64; 20 seeded directions,
     eps = 1e-6 (relative to the per-variable RMS of U0)."""
