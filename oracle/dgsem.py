@@ -48,8 +48,8 @@ import torch
 
 from .basis import diff_matrix, lgl
 from .mesh import ELEM_AXIS, NODE_AXIS, WALL, Mesh
-from .physics import (Gas, Prim, euler_flux, kg_flux, llf_flux, primitives,
-                      viscous_flux, wall_convective_flux)
+from .physics import (FLUXES, Gas, Prim, ec_flux, euler_flux, kg_flux, llf_flux, primitives,
+                      roe_flux, viscous_flux, wall_convective_flux)
 
 __all__ = ["from_flat", "to_flat", "lift", "rhs", "lsrk", "rk_step", "kinetic_energy",
            "RK_A", "RK_B", "RK_C"]
@@ -159,8 +159,14 @@ def lift(U: torch.Tensor, mesh: Mesh, gas: Gas):
 # --------------------------------------------------------------------- RHS
 
 def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
-        central_only: bool = False, source=None) -> torch.Tensor:
-    """L(U) of the split-form DGSEM (module docstring).  U: (5, *mesh.shape)."""
+        central_only: bool = False, source=None, flux: str = "kg_llf") -> torch.Tensor:
+    """L(U) of the split-form DGSEM (module docstring).  U: (5, *mesh.shape).
+    flux: "kg_llf" (Kennedy-Gruber volume flux, Lax-Friedrichs surface flux) or
+    "ec_roe" (Chandrashekar volume flux, Roe surface flux with the Harten-Hyman
+    correction, ``physics``)."""
+    if flux not in FLUXES:
+        raise ValueError(f"flux must be one of {FLUXES}")
+    ec = flux == "ec_roe"
     N, NP = mesh.N, mesh.NP
     D = diff_matrix(N)
     _, w = lgl(N)
@@ -173,7 +179,7 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
 
         # volume integral: two-point flux differencing along the d-lines
         Pi, Pm = _prim_line(P, na, -2), _prim_line(P, na, -1)
-        fsharp = kg_flux(Pi, Pm, d)
+        fsharp = ec_flux(Pi, Pm, d, gas) if ec else kg_flux(Pi, Pm, d)
         Dd = D.to(U.dtype)
         vol_c = [(2.0 * (Dd * f).sum(-1)).movedim(-1, na) for f in fsharp]
 
@@ -194,7 +200,8 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
         P_R = _prim_roll(P_lo, -1, ea)
         U_hi = [U[v].select(na, N) for v in range(5)]
         U_R = [torch.roll(U[v].select(na, 0), -1, ea) for v in range(5)]
-        Fc = llf_flux(P_hi, P_R, U_hi, U_R, d, gas, central_only)
+        Fc = roe_flux(P_hi, P_R, d, gas, central_only) if ec else \
+            llf_flux(P_hi, P_R, U_hi, U_R, d, gas, central_only)
         Fv_L = [fv[v].select(na, N) for v in range(5)]
         Fv_R = [torch.roll(fv[v].select(na, 0), -1, ea) for v in range(5)]
         F_hi = [Fc[v] - 0.5 * (Fv_L[v] + Fv_R[v]) for v in range(5)]
