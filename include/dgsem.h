@@ -54,6 +54,15 @@ typedef enum {
 #define DG_MIXED 1
 #define DG_MIXED_NOREF 2  /* DG_MIXED without the reference-state subtraction (measurement) */
 
+/* Convective fluxes (dg_physics.flux). */
+#define DG_FLUX_KG_LLF 0  /* Kennedy-Gruber split-form volume flux; local Lax-Friedrichs
+                             surface flux with the Kennedy-Gruber central part        */
+#define DG_FLUX_EC_ROE 1  /* the paper's production pair (Sec. 4): Chandrashekar's
+                             entropy-conserving volume flux; Roe surface flux with
+                             Harten's entropy correction (Harten-Hyman form), its
+                             central part the Chandrashekar flux.  DG_FP64 only; no
+                             adjoint (the VJP calls return DG_EUNSUPPORTED)            */
+
 typedef struct dg_ctx dg_ctx;
 
 /* Mesh description.  faces[d] are host arrays of nelem[d] + 1 strictly
@@ -76,7 +85,9 @@ typedef struct {
                          line sums; FP64 state, primitive recovery, surface
                          fluxes and RK accumulation; p, e and T enter the FP32
                          parts relative to a per-element reference value       */
-  int central_only;   /* 1: drop the Lax-Friedrichs dissipation (test switch)     */
+  int central_only;   /* 1: drop the surface dissipation (Lax-Friedrichs or Roe):
+                         test switch                                             */
+  int flux;           /* DG_FLUX_KG_LLF or DG_FLUX_EC_ROE                          */
 } dg_physics;
 
 /* Library version string (static storage). */
@@ -89,7 +100,8 @@ dg_status dg_lgl(int N, double* xi, double* w);
 /* Validate the mesh and physics, build the host tables and create a context
  * on `hip_stream` (a hipStream_t, NULL = default stream).  No device work.
  * Errors: DG_EINVAL (null pointers, non-monotone faces, bad bc, gamma <= 1,
- * R <= 0, mu < 0, Pr <= 0, empty mesh), DG_EUNSUPPORTED (N not in {3, 5, 7}).  */
+ * R <= 0, mu < 0, Pr <= 0, empty mesh, unknown precision or flux),
+ * DG_EUNSUPPORTED (N not in {3, 5, 7}; DG_FLUX_EC_ROE with mixed precision). */
 dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* hip_stream,
                        dg_ctx** out);
 

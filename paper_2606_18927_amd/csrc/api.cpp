@@ -104,6 +104,7 @@ dg::DevPhys dev_phys(const dg_ctx* c) {
   p.viscous = c->phys.viscous;
   p.central = c->phys.central_only;
   p.mixed_ref = c->phys.precision == DG_MIXED ? 1 : 0;
+  p.ec = c->phys.flux == DG_FLUX_EC_ROE ? 1 : 0;
   return p;
 }
 
@@ -212,6 +213,8 @@ dg_status need_adjoint(dg_ctx* c) {
   dg_status st = need_bound(c);
   if (st != DG_OK) return st;
   if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
+  if (c->phys.flux != DG_FLUX_KG_LLF)
+    return fail(c, DG_EUNSUPPORTED, "the adjoint is built for the Kennedy-Gruber / Lax-Friedrichs fluxes");
   return DG_OK;
 }
 
@@ -252,6 +255,8 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   if (phys->precision != DG_FP64 && phys->precision != DG_MIXED &&
       phys->precision != DG_MIXED_NOREF)
     return DG_EINVAL;
+  if (phys->flux != DG_FLUX_KG_LLF && phys->flux != DG_FLUX_EC_ROE) return DG_EINVAL;
+  if (phys->flux == DG_FLUX_EC_ROE && phys->precision != DG_FP64) return DG_EUNSUPPORTED;
   if (mesh->bc[0] == DG_BC_ISOTHERMAL_WALL || mesh->bc[1] == DG_BC_ISOTHERMAL_WALL ||
       mesh->bc[2] == DG_BC_ISOTHERMAL_WALL) {
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;
@@ -419,9 +424,8 @@ dg_status dg_rk_step(dg_ctx* c, double /*t*/, double dt, int nsteps) {
 }
 
 dg_status dg_eval_rhs_vjp(dg_ctx* c, const double* U, const double* lam, double* Ubar, double /*t*/) {
-  dg_status st = need_bound(c);
+  dg_status st = need_adjoint(c);
   if (st != DG_OK) return st;
-  if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
   if (!U || !lam || !Ubar || Ubar == U || Ubar == lam) return fail(c, DG_EINVAL, "bad pointers");
   const dg::DevMesh m = dev_mesh(c);
   const dg::DevPhys p = dev_phys(c);

@@ -29,6 +29,7 @@ struct DevPhys {
   double gamma, gm1, R, inv_R, mu, kappa, cv;
   int viscous, central;
   int mixed_ref;      // mixed precision: subtract the element reference state
+  int ec;             // Chandrashekar volume flux and Roe surface flux
 };
 
 // LGL tables of one N, held in device memory inside the workspace.

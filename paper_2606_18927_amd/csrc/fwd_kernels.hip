@@ -408,7 +408,7 @@ __device__ inline void line_sums_half(const R* sD, const V2 (*sp)[Geo<N>::EB], c
 
 // BR1 lifted gradients g[3 q + d] at node (i, j, k) from the half values of
 // u, v, w and from T, with the lifting corrections ssq of the six faces.
-template <int N, typename R, typename V2>
+template <int N, typename R, typename V2, bool HALF = true>
 __device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[Geo<N>::EB],
                                              const R* sT, const R (*ssq)[4][Geo<N>::NF], int i,
                                              int j, int k, R sx, R sy, R sz, R g[12]) {
@@ -418,7 +418,7 @@ __device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[Geo<N>:
   line_sums_half<N, R, 0, V2>(sD, sp, sT, i, j, k, a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    R t = c < 3 ? R(2) * a[c] : a[c];  // half values: twice the line sum (exact)
+    R t = c < 3 && HALF ? R(2) * a[c] : a[c];  // half values: twice the line sum (exact)
     if (i == 0) t += ssq[0][c][j + NP * k];
     if (i == N) t += ssq[1][c][j + NP * k];
     g[3 * c + 0] = sx * t;
@@ -427,7 +427,7 @@ __device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[Geo<N>:
   line_sums_half<N, R, 1, V2>(sD, sp, sT, i, j, k, a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    R t = c < 3 ? R(2) * a[c] : a[c];
+    R t = c < 3 && HALF ? R(2) * a[c] : a[c];
     if (j == 0) t += ssq[2][c][i + NP * k];
     if (j == N) t += ssq[3][c][i + NP * k];
     g[3 * c + 1] = sy * t;
@@ -436,7 +436,7 @@ __device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[Geo<N>:
   line_sums_half<N, R, 2, V2>(sD, sp, sT, i, j, k, a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    R t = c < 3 ? R(2) * a[c] : a[c];
+    R t = c < 3 && HALF ? R(2) * a[c] : a[c];
     if (k == 0) t += ssq[4][c][i + NP * j];
     if (k == N) t += ssq[5][c][i + NP * j];
     g[3 * c + 2] = sz * t;
@@ -499,7 +499,193 @@ __device__ inline void surface_correction(const double A[6], const double so[5],
   for (int v = 0; v < 5; ++v) corr[v] *= sc;
 }
 
-template <int N, typename R, bool RK, bool VISC>
+// ---------------------------------------------------------------------------
+// Entropy-conserving volume flux and Roe surface flux (FP64)
+// ---------------------------------------------------------------------------
+
+// Logarithmic mean (a - b) / (ln a - ln b) of positive a, b, as (a + b) / (2 F)
+// with f = (a - b) / (a + b) and F = atanh(f) / f (ln(a / b) = 2 atanh f); for
+// f^2 < 1e-4, F is its series 1 + f^2/3 + f^4/5 + f^6/7 (the first dropped
+// term is below 1.2e-17).
+__device__ inline double ln_mean(double a, double b) {
+  const double s = a + b;
+  const double f = (a - b) / s;
+  const double u = f * f;
+  const double F = u < 1e-4 ? 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0))) : atanh(f) / f;
+  return s / (2.0 * F);
+}
+
+// Chandrashekar's kinetic-energy-preserving, entropy-conserving two-point flux
+// along d (paper Sec. 4 names it as the production volume flux).  a, b =
+// (rho, u), (v, w), (beta, |u|^2) with beta = rho / (2 p); {{x}} arithmetic and
+// x_ln logarithmic means:
+//   f_rho = rho_ln {{u_d}},  f_m = f_rho {{u}} + p^ e_d,  p^ = {{rho}} / (2 {{beta}}),
+//   f_E = f_rho (1 / (2 (gamma - 1) beta_ln) - {{|u|^2}} / 2) + {{u}} . f_m.
+template <int d>
+__device__ inline void ec_flux(const double2 a[3], const double2 b[3], double gm1, double f[5]) {
+  const double rho_ln = ln_mean(a[0].x, b[0].x);
+  const double beta_ln = ln_mean(a[2].x, b[2].x);
+  const double p_hat = (a[0].x + b[0].x) / (2.0 * (a[2].x + b[2].x));
+  const double u = 0.5 * (a[0].y + b[0].y), v = 0.5 * (a[1].x + b[1].x), w = 0.5 * (a[1].y + b[1].y);
+  const double q2 = 0.5 * (a[2].y + b[2].y);
+  const double ud = d == 0 ? u : (d == 1 ? v : w);
+  const double F1 = rho_ln * ud;
+  f[0] = F1;
+  f[1] = F1 * u;
+  f[2] = F1 * v;
+  f[3] = F1 * w;
+  f[1 + d] += p_hat;
+  f[4] = F1 * (0.5 / (gm1 * beta_ln) - 0.5 * q2) + f[1] * u + f[2] * v + f[3] * w;
+}
+
+// Line sums of direction d with the entropy-conserving flux: ac = sum_m D_im
+// f#_EC(own, m), av = sum_m D_im f_v,d(m).
+template <int N, int d, bool VISC>
+__device__ inline void volume_sweep_ec(const double2 (&own)[3], int i, int j, int k, const double* sD,
+                                       const double2 (*sp)[Geo<N>::EB],
+                                       const double2 (*sfv)[Geo<N>::EB], double gm1, double ac[5],
+                                       double av[4]) {
+  using Gm = Geo<N>;
+  constexpr int NP = Gm::NP;
+  const int idx = d == 0 ? i : (d == 1 ? j : k);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) ac[v] = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) av[c] = 0.0;
+  // not unrolled: the pair flux is long, and unrolled copies keep too many
+  // values live
+#pragma unroll 1
+  for (int m = 0; m < NP; ++m) {
+    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
+    const double Dim = sD[idx * Gm::DS + m];
+    const double2 b[3] = {sp[0][lm], sp[1][lm], sp[2][lm]};
+    double f[5];
+    ec_flux<d>(own, b, gm1, f);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ac[v] += Dim * f[v];
+    if (VISC) {
+      const double2 f01 = sfv[0][lm], f23 = sfv[1][lm];
+      av[0] += Dim * f01.x;
+      av[1] += Dim * f01.y;
+      av[2] += Dim * f23.x;
+      av[3] += Dim * f23.y;
+    }
+  }
+}
+
+// |lambda| with Harten's entropy correction in the Harten-Hyman form:
+// (lambda^2 + delta^2) / (2 delta) where |lambda| < delta,
+// delta = max(0, lambda - lambda_L, lambda_R - lambda).
+__device__ inline double hh_abs(double lam, double lam_L, double lam_R) {
+  double delta = fmax(lam - lam_L, lam_R - lam);
+  delta = delta > 0.0 ? delta : 0.0;
+  return fabs(lam) < delta ? (lam * lam + delta * delta) / (2.0 * delta) : fabs(lam);
+}
+
+// Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with normal e_d
+// (L = lower side, R = upper side; primitives (rho, u, v, w, p) and total
+// energies E), linearised at the Roe average: sqrt(rho)-weighted u and
+// H = (E + p) / rho, rho~ = sqrt(rho_L rho_R), a~^2 = (gamma - 1)(H~ - |u~|^2 / 2).
+// Waves: acoustic u~_d -+ a~, alpha = ([[p]] -+ rho~ a~ [[u_d]]) / (2 a~^2),
+// r = (1, u~ -+ a~ e_d, H~ -+ u~_d a~) (eigenvalues with the correction above);
+// entropy u~_d, alpha = [[rho]] - [[p]] / a~^2, r = (1, u~, |u~|^2 / 2); shear
+// u~_d with rho~ (0, [[u_t]], u~ . [[u_t]]).
+template <int d>
+__device__ inline void roe_dissipation(const double L[5], double EL, const double R[5], double ER,
+                                       double gamma, double D[5]) {
+  const double sl = sqrt(L[0]), sr = sqrt(R[0]);
+  const double isum = 1.0 / (sl + sr);
+  const double wl = sl * isum, wr = sr * isum;
+  double ut[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ut[c] = wl * L[1 + c] + wr * R[1 + c];
+  const double H = wl * (EL + L[4]) / L[0] + wr * (ER + R[4]) / R[0];
+  const double q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const double a2 = (gamma - 1.0) * (H - 0.5 * q2);
+  const double a = sqrt(a2);
+  const double rho = sl * sr;
+  const double un = ut[d];
+  const double dp = R[4] - L[4];
+  double du[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) du[c] = R[1 + c] - L[1 + c];
+  const double al1 = (dp - rho * a * du[d]) / (2.0 * a2);
+  const double al5 = (dp + rho * a * du[d]) / (2.0 * a2);
+  const double al2 = (R[0] - L[0]) - dp / a2;
+  const double cl = sqrt(gamma * L[4] / L[0]), cr = sqrt(gamma * R[4] / R[0]);
+  const double l1 = hh_abs(un - a, L[1 + d] - cl, R[1 + d] - cr);
+  const double l5 = hh_abs(un + a, L[1 + d] + cl, R[1 + d] + cr);
+  const double l2 = fabs(un);
+  const double t1 = l1 * al1, t5 = l5 * al5, t2 = l2 * al2, ts = l2 * rho;
+  double udt = 0.0;
+  D[0] = t1 + t2 + t5;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double sh = c == d ? 0.0 : du[c];
+    udt += ut[c] * sh;
+    D[1 + c] = t1 * ut[c] + t2 * ut[c] + t5 * ut[c] + ts * sh;
+  }
+  D[1 + d] += (t5 - t1) * a;
+  D[4] = t1 * (H - un * a) + t2 * (0.5 * q2) + t5 * (H + un * a) + ts * udt;
+}
+
+// Surface correction of one face task with the entropy-conserving / Roe pair
+// (FP64): ((F*_c - F*_v) - (f_c - f_v)(own)) (+-1/w_end),
+// F*_c = f#_EC(U_L, U_R) - (1/2) Roe dissipation.  A = own (rho, u, v, w, p,
+// beta), q2o = own |u|^2; so, sn: own and neighbour conservative states.
+template <int d>
+__device__ inline void surface_correction_ec(const double A[6], double q2o, const double so[5],
+                                             const double sn[5], bool wall, bool up,
+                                             const double fvo[4], const double fvn[4],
+                                             const DevPhys& ph, double inv_w, double corr[5]) {
+  const double po = A[4];
+  {
+    const double ud = A[1 + d];
+    const double mass = A[0] * ud;
+    corr[0] = -mass;
+    corr[1] = -mass * A[1] + fvo[0];
+    corr[2] = -mass * A[2] + fvo[1];
+    corr[3] = -mass * A[3] + fvo[2];
+    corr[1 + d] -= po;
+    corr[4] = -(so[4] + po) * ud + fvo[3];
+  }
+  if (wall) {
+    corr[1 + d] += po;
+    corr[1] -= fvo[0];
+    corr[2] -= fvo[1];
+    corr[3] -= fvo[2];
+    corr[4] -= fvo[3] - (A[1] * fvo[0] + A[2] * fvo[1] + A[3] * fvo[2]);
+  } else {
+    const double irn = 1.0 / sn[0];
+    const double B[5] = {sn[0], sn[1] * irn, sn[2] * irn, sn[3] * irn, 0.0};
+    const double q2n = B[1] * B[1] + B[2] * B[2] + B[3] * B[3];
+    const double pn = ph.gm1 * (sn[4] - 0.5 * sn[0] * q2n);
+    const double Bf[5] = {B[0], B[1], B[2], B[3], pn};
+    const double2 a[3] = {double2{A[0], A[1]}, double2{A[2], A[3]}, double2{A[5], q2o}};
+    const double2 b[3] = {double2{B[0], B[1]}, double2{B[2], B[3]}, double2{0.5 * sn[0] / pn, q2n}};
+    double F[5];
+    ec_flux<d>(a, b, ph.gm1, F);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) corr[v] += F[v];
+    if (!ph.central) {
+      const double Ao[5] = {A[0], A[1], A[2], A[3], po};
+      double Dr[5];
+      if (up)
+        roe_dissipation<d>(Ao, so[4], Bf, sn[4], ph.gamma, Dr);
+      else
+        roe_dissipation<d>(Bf, sn[4], Ao, so[4], ph.gamma, Dr);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) corr[v] -= 0.5 * Dr[v];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) corr[1 + c] -= 0.5 * (fvo[c] + fvn[c]);
+  }
+  const double sc = up ? inv_w : -inv_w;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) corr[v] *= sc;
+}
+
+template <int N, typename R, bool RK, bool VISC, bool EC>
 __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs(const double* __restrict__ U,
                                                      const R* __restrict__ ffv,
                                                      double* __restrict__ out,
@@ -511,8 +697,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
   constexpr bool MIXED = sizeof(R) == 4;
   using V2 = typename V2T<R>::type;
+  static_assert(!EC || !MIXED, "the entropy-conserving pair is FP64 only");
   __shared__ R sD[NP * Gm::DS];
-  __shared__ V2 sp[EPB][3][EB];     // halves of (rho, u), (v, w), (p - p_ref, e - e_ref)
+  // halves of (rho, u), (v, w), (p - p_ref, e - e_ref); with EC the full values
+  // (rho, u), (v, w), (beta, |u|^2)
+  __shared__ V2 sp[EPB][3][EB];
   __shared__ V2 sfv[EPB][2][EB];    // f_v,d of the current direction; T - T_ref in P1-P2
   // sX: lifting corrections (P1-P2, as ssq), own f_v,d of the face nodes in
   // components 0..3 (P3-P4), surface corrections (P4-P5).  In P4 every face
@@ -602,12 +791,21 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     uo = static_cast<R>(P.u);
     vo = static_cast<R>(P.v);
     wo = static_cast<R>(P.w);
-    own[0].x = static_cast<R>(0.5 * P.rho);
-    own[0].y = static_cast<R>(0.5 * P.u);
-    own[1].x = static_cast<R>(0.5 * P.v);
-    own[1].y = static_cast<R>(0.5 * P.w);
-    own[2].x = static_cast<R>(0.5 * (P.p - p_ref));
-    own[2].y = static_cast<R>(0.5 * (P.e - e_ref));
+    if (EC) {
+      own[0].x = P.rho;
+      own[0].y = P.u;
+      own[1].x = P.v;
+      own[1].y = P.w;
+      own[2].x = 0.5 * P.rho / P.p;
+      own[2].y = P.u * P.u + P.v * P.v + P.w * P.w;
+    } else {
+      own[0].x = static_cast<R>(0.5 * P.rho);
+      own[0].y = static_cast<R>(0.5 * P.u);
+      own[1].x = static_cast<R>(0.5 * P.v);
+      own[1].y = static_cast<R>(0.5 * P.w);
+      own[2].x = static_cast<R>(0.5 * (P.p - p_ref));
+      own[2].y = static_cast<R>(0.5 * (P.e - e_ref));
+    }
 #pragma unroll
     for (int q = 0; q < 3; ++q) sp[le][q][l] = own[q];
     if (VISC) sT[l] = static_cast<R>(P.T - T_ref);
@@ -621,7 +819,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
       const R* sTf = reinterpret_cast<const R*>(&sfv[ft.le][0][0]);
       const V2 ru = sp[ft.le][0][lo], vw = sp[ft.le][1][lo];
-      const double qo[4] = {2.0 * ru.y, 2.0 * vw.x, 2.0 * vw.y, sTf[lo]};
+      constexpr double hv = EC ? 1.0 : 2.0;  // sp holds halves unless EC
+      const double qo[4] = {hv * ru.y, hv * vw.x, hv * vw.y, sTf[lo]};
       double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
       if (!fwall) {
         const Prim Pn = primitives(sn, ph);
@@ -645,7 +844,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   if (VISC) {
     if (active) {
       R g[12];
-      lifted_gradients_half<N, R, V2>(sD, sp[le], sT, ssq[le], i, j, k,
+      lifted_gradients_half<N, R, V2, !EC>(sD, sp[le], sT, ssq[le], i, j, k,
                                       static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
                                       static_cast<R>(mesh.s[2][ez]), g);
       stress<R>(g, mu, kappa, tau, qT);
@@ -672,8 +871,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     }                                                                                       \
     __syncthreads();                                                                        \
     if (active) {                                                                           \
-      R ac[5], av[4], du;                                                                   \
-      volume_sweep<N, R, D, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sfv[le], ac, av, du); \
+      R ac[5], av[4], du = R(0);                                                            \
+      if constexpr (EC)                                                                     \
+        volume_sweep_ec<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le], ph.gm1, ac, av);     \
+      else                                                                                  \
+        volume_sweep<N, R, D, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sfv[le], ac, av, du); \
       const double sd = mesh.s[D][D == 0 ? ex : (D == 1 ? ey : ez)];                         \
       ut[0] -= sd * static_cast<double>(R(2) * ac[0]);                                      \
       _Pragma("unroll") for (int c = 0; c < 4; ++c)                                         \
@@ -711,12 +913,24 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
       for (int c = 0; c < 4; ++c) fvn[c] = static_cast<double>(src[c * NF]);
     }
-    double A[6], so[5], sn[5];
+    double A[6], so[5], sn[5], q2o = 0.0;
     if (MIXED) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) so[v] = sO[ft.le][ft.f][v][ft.ab];
       const Prim P = primitives(so, ph);
       A[0] = P.rho; A[1] = P.u; A[2] = P.v; A[3] = P.w; A[4] = P.p; A[5] = P.e;
+    } else if (EC) {
+      // (rho, u, v, w, beta, |u|^2) from sp; p and E recovered from them
+      const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
+      const V2 a0 = sp[ft.le][0][lo], a1 = sp[ft.le][1][lo], a2 = sp[ft.le][2][lo];
+      A[0] = a0.x; A[1] = a0.y; A[2] = a1.x; A[3] = a1.y;
+      A[4] = 0.5 * a0.x / a2.x; A[5] = a2.x;
+      q2o = a2.y;
+      so[0] = A[0];
+      so[1] = A[0] * A[1];
+      so[2] = A[0] * A[2];
+      so[3] = A[0] * A[3];
+      so[4] = A[4] / ph.gm1 + 0.5 * A[0] * q2o;
     } else {
       // FP64: the halves in sp are exact, and p_ref = e_ref = 0
       const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
@@ -736,9 +950,15 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int c = 0; c < 4; ++c) fvo[c] = static_cast<double>(sX[ft.le][ft.f][c][ft.ab]);
     }
     double corr[5];
-    if (ft.d == 0) surface_correction<0>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
-    if (ft.d == 1) surface_correction<1>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
-    if (ft.d == 2) surface_correction<2>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    if constexpr (EC) {
+      if (ft.d == 0) surface_correction_ec<0>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+      if (ft.d == 1) surface_correction_ec<1>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+      if (ft.d == 2) surface_correction_ec<2>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    } else {
+      if (ft.d == 0) surface_correction<0>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+      if (ft.d == 1) surface_correction<1>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+      if (ft.d == 2) surface_correction<2>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sX[ft.le][ft.f][v][ft.ab] = static_cast<R>(corr[v]);
   }
@@ -781,16 +1001,33 @@ hipError_t face_flux_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, co
   return hipGetLastError();
 }
 
+template <int N, typename R, bool RK, bool VISC, bool EC>
+void launch_k_rhs(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
+                  const void* ffv, double* out, double* U_out, const Stage& st, int* status,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((k_rhs<N, R, RK, VISC, EC>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s,
+                     U, static_cast<const R*>(ffv), out, U_out, m, p, b, st, status);
+}
+
 template <int N, typename R, bool RK>
 hipError_t rhs_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
                  const void* ffv, double* out, double* U_out, const Stage& st, int* status,
                  hipStream_t s) {
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (p.ec) {
+      if (p.viscous)
+        launch_k_rhs<N, R, RK, true, true>(m, p, b, U, ffv, out, U_out, st, status, s);
+      else
+        launch_k_rhs<N, R, RK, false, true>(m, p, b, U, ffv, out, U_out, st, status, s);
+      return hipGetLastError();
+    }
+  } else {
+    if (p.ec) return hipErrorInvalidValue;  // rejected at init: FP64 only
+  }
   if (p.viscous)
-    hipLaunchKernelGGL((k_rhs<N, R, RK, true>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s,
-                       U, static_cast<const R*>(ffv), out, U_out, m, p, b, st, status);
+    launch_k_rhs<N, R, RK, true, false>(m, p, b, U, ffv, out, U_out, st, status, s);
   else
-    hipLaunchKernelGGL((k_rhs<N, R, RK, false>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s,
-                       U, static_cast<const R*>(ffv), out, U_out, m, p, b, st, status);
+    launch_k_rhs<N, R, RK, false, false>(m, p, b, U, ffv, out, U_out, st, status, s);
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ESTATE", 3: "DG_EHIP", 4: "DG
                 5: "DG_EUNSUPPORTED"}
 BC = {"periodic": 0, "wall": 1}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed_noref": 2}
+FLUX = {"kg_llf": 0, "ec_roe": 1}
 
 
 class DgsemError(RuntimeError):
@@ -42,7 +43,7 @@ class MeshDesc(ctypes.Structure):
 class Physics(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("R", ctypes.c_double), ("mu", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("viscous", ctypes.c_int), ("precision", ctypes.c_int),
-                ("central_only", ctypes.c_int)]
+                ("central_only", ctypes.c_int), ("flux", ctypes.c_int)]
 
 
 _P = ctypes.c_void_p
@@ -143,7 +144,7 @@ class Solver:
 
     def __init__(self, mesh: MeshSpec, gamma: float, R: float, mu: float, Pr: float, *,
                  viscous: bool = True, precision: str = "fp64", central_only: bool = False,
-                 with_adjoint: bool = False, device=None):
+                 flux: str = "kg_llf", with_adjoint: bool = False, device=None):
         L = lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
@@ -156,7 +157,8 @@ class Solver:
             desc.faces[d] = self._faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             desc.bc[d] = BC[mesh.bc[d]]
         desc.T_wall = mesh.T_wall
-        phys = Physics(gamma, R, mu, Pr, 1 if viscous else 0, PRECISION[precision], 1 if central_only else 0)
+        phys = Physics(gamma, R, mu, Pr, 1 if viscous else 0, PRECISION[precision], 1 if central_only else 0,
+                       FLUX[flux])
         ctx = _P()
         st = L.dg_init_mesh(ctypes.byref(desc), ctypes.byref(phys), self.stream.cuda_stream, ctypes.byref(ctx))
         if st != DG_OK:
@@ -288,9 +290,9 @@ class Solver:
 
 
 def solver_for(workload, *, device=None, with_adjoint=False, precision=None, viscous=True,
-               central_only=False) -> Solver:
+               central_only=False, flux=None) -> Solver:
     """Solver for a paper_2606_18927_amd.workloads.Workload."""
     mesh = MeshSpec(workload.N, workload.faces(), workload.bc, workload.T_wall)
     return Solver(mesh, workload.gamma, workload.R, workload.mu, workload.Pr, viscous=viscous,
                   precision=precision or workload.precision, central_only=central_only,
-                  with_adjoint=with_adjoint, device=device)
+                  flux=flux or workload.flux, with_adjoint=with_adjoint, device=device)

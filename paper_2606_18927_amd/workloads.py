@@ -58,6 +58,7 @@ class Workload:
     seed: int = TGV_SEED
     cfl: float = 0.5
     checkpoint_every: int = 0
+    flux: str = "kg_llf"      # "kg_llf" | "ec_roe"
     extra: dict = field(default_factory=dict)
 
     # gas / physics parameters -------------------------------------------
@@ -109,6 +110,9 @@ WORKLOADS = {
                                 noise=0.01, seed=TGV_SEED),
     "tgv_n7_32x32x32_mixed": Workload("tgv_n7_32x32x32_mixed", "tgv", 7, (32, 32, 32),
                                       nsteps=100, noise=0.01, seed=TGV_SEED, precision="mixed"),
+    # the same with the entropy-conserving volume flux and the Roe surface flux
+    "tgv_n7_32x32x32_ec": Workload("tgv_n7_32x32x32_ec", "tgv", 7, (32, 32, 32), nsteps=100,
+                                   noise=0.01, seed=TGV_SEED, flux="ec_roe"),
     # stretched channel for the adjoint: N=5, 16^3 elements, 50 steps
     "channel_n5_16x16x16": Workload("channel_n5_16x16x16", "channel", 5, (16, 16, 16),
                                     nsteps=50, seed=CHANNEL_SEED),

@@ -70,10 +70,10 @@ def _init(L, desc, phys):
 
 
 def _phys(**kw):
-    base = dict(gamma=1.4, R=1.0, mu=0.01, Pr=0.72, viscous=1, precision=0, central_only=0)
+    base = dict(gamma=1.4, R=1.0, mu=0.01, Pr=0.72, viscous=1, precision=0, central_only=0, flux=0)
     base.update(kw)
     return dgsem.Physics(base["gamma"], base["R"], base["mu"], base["Pr"], base["viscous"],
-                         base["precision"], base["central_only"])
+                         base["precision"], base["central_only"], base["flux"])
 
 
 def test_init_mesh_validation_errors(L):
@@ -83,6 +83,13 @@ def test_init_mesh_validation_errors(L):
     L.dg_free(ctx)
     d, keep = _desc(N=4)
     assert _init(L, d, _phys())[0] == dgsem.DG_EUNSUPPORTED
+    # flux choice: the entropy-conserving / Roe pair is FP64 only; unknown values are rejected
+    d, keep = _desc()
+    st, ctx = _init(L, d, _phys(flux=1))
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
+    assert _init(L, d, _phys(flux=1, precision=1))[0] == dgsem.DG_EUNSUPPORTED
+    assert _init(L, d, _phys(flux=2))[0] == dgsem.DG_EINVAL
     d, keep = _desc(faces=(np.array([0.0, 0.5, 0.4]), np.linspace(0, 1, 3), np.linspace(0, 1, 3)))
     assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL          # non-monotone faces
     d, keep = _desc(bc=(0, 7, 0))
