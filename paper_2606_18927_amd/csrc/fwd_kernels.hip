@@ -503,16 +503,34 @@ __device__ inline void surface_correction(const double A[6], const double so[5],
 // Entropy-conserving volume flux and Roe surface flux (FP64)
 // ---------------------------------------------------------------------------
 
-// Logarithmic mean (a - b) / (ln a - ln b) of positive a, b, as (a + b) / (2 F)
-// with f = (a - b) / (a + b) and F = atanh(f) / f (ln(a / b) = 2 atanh f); for
-// f^2 < 1e-4, F is its series 1 + f^2/3 + f^4/5 + f^6/7 (the first dropped
-// term is below 1.2e-17).
-__device__ inline double ln_mean(double a, double b) {
-  const double s = a + b;
-  const double f = (a - b) / s;
-  const double u = f * f;
-  const double F = u < 1e-4 ? 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0))) : atanh(f) / f;
-  return s / (2.0 * F);
+// 1 / x for x > 0 of moderate size: the hardware reciprocal estimate refined
+// by two Newton-Raphson steps r <- r + r (1 - x r).
+__device__ inline double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Means of the entropy-conserving flux for one pair: rho_ln and 1 / beta_ln
+// (logarithmic means) and p^ = {{rho}} / (2 {{beta}}).  The logarithmic mean of
+// positive a, b is (a - b) / (ln a - ln b) = (a + b) / (2 F), F = atanh(f) / f,
+// f = (a - b) / (a + b) (ln(a / b) = 2 atanh f).  For f^2 < 1e-4 F is its
+// series 1 + f^2/3 + f^4/5 + f^6/7 and 1 / F the series
+// 1 - f^2/3 - 4 f^4/45 - 44 f^6/945 (first dropped terms below 1.2e-17 and
+// 3.1e-18), so the common case costs two reciprocals and no logarithm.
+__device__ inline void ec_means(double ra, double rb, double ba, double bb, double& rho_ln,
+                                double& inv_beta_ln, double& p_hat) {
+  const double sr = ra + rb, sb = ba + bb;
+  const double ir = rcp_nr(sr), ib = rcp_nr(sb);
+  const double fr = (ra - rb) * ir, fb = (ba - bb) * ib;
+  const double ur = fr * fr, ub = fb * fb;
+  rho_ln = 0.5 * sr * (1.0 - ur * (1.0 / 3.0 + ur * (4.0 / 45.0 + ur * (44.0 / 945.0))));
+  inv_beta_ln = 2.0 * ib * (1.0 + ub * (1.0 / 3.0 + ub * (0.2 + ub * (1.0 / 7.0))));
+  if (ur >= 1e-4) rho_ln = 0.5 * sr * fr / atanh(fr);
+  if (ub >= 1e-4) inv_beta_ln = 2.0 * ib * atanh(fb) / fb;
+  p_hat = 0.5 * sr * ib;
 }
 
 // Chandrashekar's kinetic-energy-preserving, entropy-conserving two-point flux
@@ -523,9 +541,8 @@ __device__ inline double ln_mean(double a, double b) {
 //   f_E = f_rho (1 / (2 (gamma - 1) beta_ln) - {{|u|^2}} / 2) + {{u}} . f_m.
 template <int d>
 __device__ inline void ec_flux(const double2 a[3], const double2 b[3], double gm1, double f[5]) {
-  const double rho_ln = ln_mean(a[0].x, b[0].x);
-  const double beta_ln = ln_mean(a[2].x, b[2].x);
-  const double p_hat = (a[0].x + b[0].x) / (2.0 * (a[2].x + b[2].x));
+  double rho_ln, inv_beta_ln, p_hat;
+  ec_means(a[0].x, b[0].x, a[2].x, b[2].x, rho_ln, inv_beta_ln, p_hat);
   const double u = 0.5 * (a[0].y + b[0].y), v = 0.5 * (a[1].x + b[1].x), w = 0.5 * (a[1].y + b[1].y);
   const double q2 = 0.5 * (a[2].y + b[2].y);
   const double ud = d == 0 ? u : (d == 1 ? v : w);
@@ -535,7 +552,7 @@ __device__ inline void ec_flux(const double2 a[3], const double2 b[3], double gm
   f[2] = F1 * v;
   f[3] = F1 * w;
   f[1 + d] += p_hat;
-  f[4] = F1 * (0.5 / (gm1 * beta_ln) - 0.5 * q2) + f[1] * u + f[2] * v + f[3] * w;
+  f[4] = F1 * (0.5 / gm1 * inv_beta_ln - 0.5 * q2) + f[1] * u + f[2] * v + f[3] * w;
 }
 
 // Line sums of direction d with the entropy-conserving flux: ac = sum_m D_im
