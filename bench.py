@@ -11,6 +11,8 @@ paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
                 its mean launch time (HIP events on the launch stream) vs 8 TB/s;
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same step in mixed precision (when requested / available);
+  ec_roe        the same step with the entropy-conserving volume flux and the
+                Roe surface flux (FP64);
   adjoint       adjoint/forward time ratio (when available).
 """
 
@@ -74,6 +76,7 @@ def _parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-ec", action="store_true", help="skip the entropy-conserving / Roe flux leg")
     ap.add_argument("--adjoint-steps", type=int, default=50)
     return ap.parse_args()
 
@@ -272,6 +275,16 @@ def main():
             print(f"[bench] mixed {mixed['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
         except dgsem.DgsemError as e:
             mixed = {"error": str(e)}
+    ec = None
+    if not args.no_ec and wl.name == "tgv_n7_32x32x32":
+        # the paper's production flux pair on the same workload, FP64
+        wl_ec = workloads.WORKLOADS["tgv_n7_32x32x32_ec"]
+        r, _ = run_precision(wl_ec, U, dt, "fp64", args.steps, args.warmup)
+        ec = {"workload": wl_ec.name, "flux": "ec_roe", "ns_per_dof_stage": r["ns_per_dof_stage"],
+              "ms_per_step": r["ms_per_step"], "rk_kernel_ms": r["rk_kernel_ms"],
+              "face_kernel_ms": r["face_kernel_ms"], "step_alg_gbs": r["step_alg_gbs"],
+              "step_frac": r["step_alg_gbs"] / HBM_PEAK_GBS}
+        print(f"[bench] ec_roe {ec['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint(args.adjoint_steps, 25)
@@ -322,6 +335,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "mixed": mixed,
+        "ec_roe": ec,
         "adjoint": adjoint,
         "context_mi300a_pid_ns": {"range": [2.457, 4.260], "note": "paper Table 1, 32 APUs, N=7 free stream"},
     }
