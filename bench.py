@@ -48,11 +48,12 @@ def alg_bytes(precision: str, N: int = 7):
 # fraction of this design's own algorithmic bytes.
 STORED_GRADIENT_BYTES_PER_DOF = 392.0
 
-# HBM bytes per launch of k_rhs<7,double> on this workload, from the rocprofv3
-# FETCH_SIZE and WRITE_SIZE passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md:
-# reads 2 x 1,136,139.45 KiB, writes 1,310,720 KiB).  Valid only for the kernel
-# sources it was counted on; reported as null once they change.
-COUNTED_TRAFFIC = {"sources_sha256_prefix": "2a2b8c0153df4214", "bytes_per_launch": 3668990881.0}
+# HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
+# counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
+# 128 x 14,195,584.7 TCC_EA0_RDREQ_128B + 64 x 2,376.3 RDREQ_64B, writes
+# WRITE_SIZE 1,310,720 KiB.  Valid only for the kernel sources it was counted
+# on; reported as null once they change.
+COUNTED_TRAFFIC = {"sources_sha256_prefix": "1fb10bdf3560efaf", "bytes_per_launch": 3159364206.0}
 TRAFFIC_SOURCES = ("fwd_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 
 
@@ -319,7 +320,7 @@ def main():
             "unit": "GB/s",
             "frac": fp64["rk_kernel_gbs"] / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+            "traffic_unit": "bytes per launch (rocprofv3 TCC_EA0_RDREQ_{32,64,128}B + WRITE_SIZE)",
             "traffic_over_algorithmic": None if traffic is None else traffic / fp64["rk_bytes_per_launch"],
             "traffic_gbs": None if traffic is None else traffic / (fp64["rk_kernel_ms"] / 1e3) / 1e9,
             "kernel_ms": fp64["rk_kernel_ms"],
