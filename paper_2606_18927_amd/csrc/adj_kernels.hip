@@ -350,7 +350,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_b(const double* __restrict__
                                                        const double* __restrict__ gbar,
                                                        const double* __restrict__ ubar,
                                                        double* __restrict__ out, double scale,
-                                                       DevMesh mesh, DevPhys ph,
+                                                       double* __restrict__ cot, double cot_a,
+                                                       double cot_b, DevMesh mesh, DevPhys ph,
                                                        DevBasis basis) {
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP, NF = Gm::NF, NN = Gm::NN, EB = Gm::EB, DS = Gm::DS;
@@ -437,8 +438,14 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_b(const double* __restrict__
     prim_vjp(s, Pb, qb[3], ph, Ub);
   }
   if (ACC) {
+    // out += scale Ubar; with cot, also the next RK stage cotangent
+    // cot <- cot_a cot + cot_b out at this node (no workgroup reads cot here)
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * stride + idx] += scale * Ub[v];
+    for (int v = 0; v < 5; ++v) {
+      const double nv = out[v * stride + idx] + scale * Ub[v];
+      out[v * stride + idx] = nv;
+      if (cot) cot[v * stride + idx] = cot_a * cot[v * stride + idx] + cot_b * nv;
+    }
   } else {
 #pragma unroll
     for (int v = 0; v < 5; ++v) out[v * stride + idx] = Ub[v];
@@ -455,17 +462,17 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
 template <int N>
 hipError_t vjp_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
                  const double* grad, const double* lam, double* gbar, double* ubar, double* out,
-                 bool acc, double scale, hipStream_t s) {
+                 bool acc, double scale, double* cot, double cot_a, double cot_b, hipStream_t s) {
   hipLaunchKernelGGL((k_vjp_a<N>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U, grad, lam,
                      gbar, ubar, m, p, b);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (acc)
     hipLaunchKernelGGL((k_vjp_b<N, true>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U,
-                       gbar, ubar, out, scale, m, p, b);
+                       gbar, ubar, out, scale, cot, cot_a, cot_b, m, p, b);
   else
     hipLaunchKernelGGL((k_vjp_b<N, false>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U,
-                       gbar, ubar, out, scale, m, p, b);
+                       gbar, ubar, out, scale, static_cast<double*>(nullptr), 0.0, 0.0, m, p, b);
   return hipGetLastError();
 }
 
@@ -474,12 +481,13 @@ hipError_t vjp_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const do
 hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
                           const double* U, const double* grad, const double* lam, double* gbar,
                           double* ubar, double* out, bool accumulate, double scale,
-                          hipStream_t s) {
+                          hipStream_t s, double* cot, double cot_a, double cot_b) {
   if (m.nE <= 0) return hipSuccess;
+  if (cot && !accumulate) return hipErrorInvalidValue;
   switch (N) {
-    case 3: return vjp_n<3>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, s);
-    case 5: return vjp_n<5>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, s);
-    case 7: return vjp_n<7>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, s);
+    case 3: return vjp_n<3>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
+    case 5: return vjp_n<5>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
+    case 7: return vjp_n<7>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -190,18 +190,21 @@ dg_status reverse_stages(dg_ctx* c, In stage_in, double dt, const double* lam_np
   if ((st = hip_check(c, hipMemcpyAsync(c->lamU, lam_np1, bytes, hipMemcpyDeviceToDevice, c->stream),
                       "lam copy")) != DG_OK)
     return st;
+  // cot_4 = B_4 lamU (A_5 = 0); each later cot_{s-1} = A_s cot_s + B_{s-1} lamU is
+  // formed by the VJP kernel of stage s right after it updates lamU
   if ((st = hip_check(c, hipMemsetAsync(c->lamG, 0, bytes, c->stream), "clear lamG")) != DG_OK) return st;
+  if ((st = hip_check(c, dg::launch_axpby(c->lamG, c->lamU, 0.0, kRkB[4], 5 * c->n_dof, c->stream),
+                      "axpby kernel")) != DG_OK)
+    return st;
   for (int s = 4; s >= 0; --s) {
-    const double a_next = s < 4 ? kRkA[s + 1] : 0.0;
-    if ((st = hip_check(c, dg::launch_axpby(c->lamG, c->lamU, a_next, kRkB[s], 5 * c->n_dof, c->stream),
-                        "axpby kernel")) != DG_OK)
-      return st;
     if (c->phys.viscous &&
         (st = hip_check(c, dg::launch_lift(c->N, m, p, b, stage_in(s), c->agrad, c->stream),
                         "lift kernel")) != DG_OK)
       return st;
     if ((st = hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, stage_in(s), c->agrad, c->lamG, c->gbar,
-                                              c->ubar, c->lamU, true, dt, c->stream),
+                                              c->ubar, c->lamU, true, dt, c->stream,
+                                              s > 0 ? c->lamG : nullptr, kRkA[s],
+                                              s > 0 ? kRkB[s - 1] : 0.0),
                         "vjp kernels")) != DG_OK)
       return st;
   }

@@ -62,10 +62,14 @@ hipError_t launch_lift(int N, const DevMesh& m, const DevPhys& p, const DevBasis
 // Adjoint (adj_kernels.hip): Ubar = (dL/dU)^T lam at U, given the forward
 // gradients grad of U; gbar and ubar are scratch (12 and 5 values per DOF).
 // accumulate: out += scale * Ubar, else out = Ubar.
+// With accumulate, cot (optional) receives the next RK stage cotangent
+// cot_a cot + cot_b out after out is updated (node by node, fused in the
+// second kernel).
 hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
                           const double* U, const double* grad, const double* lam, double* gbar,
                           double* ubar, double* out, bool accumulate, double scale,
-                          hipStream_t s);
+                          hipStream_t s, double* cot = nullptr, double cot_a = 0.0,
+                          double cot_b = 0.0);
 // y = a y + b x over n doubles.
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
