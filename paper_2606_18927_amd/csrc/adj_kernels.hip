@@ -3,10 +3,11 @@
 // Ubar = (dL/dU)^T lam is evaluated as a gather: every element computes the
 // cotangent of its own nodal state and pulls what its neighbours' equations
 // contribute through shared face nodes, so no atomics are needed and the
-// result is deterministic.  Two kernels (after k_lift has recomputed the
-// forward gradients of U):
+// result is deterministic.  Two kernels:
 //
-//   k_vjp_a : lam (+ neighbour lam at face nodes), U, grad ->
+//   k_vjp_a : lam (+ neighbour lam at face nodes), U ->
+//             the forward BR1 gradients of U (recomputed in LDS, as in the
+//             forward right-hand side), then
 //             gbar = cotangent of the lifted gradients (12 per node) and the
 //             part of Ubar that does not pass through the lifting:
 //               * volume split form: for each line pair (i, m),
@@ -183,7 +184,6 @@ __device__ inline double nb_scale(const DevMesh& m, int ex, int ey, int ez, int 
 // few registers over 256 and runs one wave per SIMD.
 template <int N>
 __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp_a(const double* __restrict__ U,
-                                                       const double* __restrict__ grad,
                                                        const double* __restrict__ lam,
                                                        double* __restrict__ gbar,
                                                        double* __restrict__ ubar, DevMesh mesh,
@@ -196,6 +196,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
   __shared__ double sL[EPB][5][EB];
   __shared__ double sFU[EPB][6][5][NF];
   __shared__ double sFV[EPB][6][5][NF];
+  __shared__ double sT[EPB][EB];          // T, for the forward lifting
+  __shared__ double ssq[EPB][6][4][NF];   // BR1 lifting corrections of the faces
 
   const int tid = threadIdx.x;
   const long long nE = mesh.nE;
@@ -225,6 +227,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
     for (int q = 0; q < 6; ++q) sP[le][q][l] = own[q];
 #pragma unroll
     for (int v = 0; v < 5; ++v) sL[le][v][l] = lo[v];
+    sT[le][l] = own[4] * ph.inv_R / own[0];
   }
   if (tid < n_face_tasks<N>()) {
     const FaceTask<N> ft(tid);
@@ -246,6 +249,22 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
         s_n = nb_scale(mesh, fx, fy, fz, ft.d, ft.up);
       }
       const double s_o = mesh.s[ft.d][ft.d == 0 ? fx : (ft.d == 1 ? fy : fz)];
+      if (ph.viscous) {
+        // forward lifting correction (q* - q_own) (+-1/w_end) of this face node
+        const Prim Po = primitives(so, ph);
+        const double qo[4] = {Po.u, Po.v, Po.w, Po.T};
+        double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+        if (!wall) {
+          const Prim Pn = primitives(sn, ph);
+          qs[0] = 0.5 * (qo[0] + Pn.u);
+          qs[1] = 0.5 * (qo[1] + Pn.v);
+          qs[2] = 0.5 * (qo[2] + Pn.w);
+          qs[3] = 0.5 * (qo[3] + Pn.T);
+        }
+        const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = (qs[c] - qo[c]) * sc;
+      }
       double Ud[5], Fvb[4], om;
       if (ft.d == 0)
         face_vjp<0>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
@@ -266,9 +285,33 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
   // P2: node lanes
   const bool visc = ph.viscous != 0;
   const double mu = ph.mu, kappa = ph.kappa;
+  // forward BR1 gradients g[3 q + d] of q = (u, v, w, T) at this node
   double g[12];
 #pragma unroll
-  for (int c = 0; c < 12; ++c) g[c] = visc ? grad[c * stride + e * NN + node] : 0.0;
+  for (int c = 0; c < 12; ++c) g[c] = 0.0;
+  if (visc) {
+    const double sx = mesh.s[0][ex], sy = mesh.s[1][ey], sz = mesh.s[2][ez];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double* q = c < 3 ? sP[le][1 + c] : sT[le];
+      double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        ax += sD[i * DS + m] * q[Gm::lds(m, j, k)];
+        ay += sD[j * DS + m] * q[Gm::lds(i, m, k)];
+        az += sD[k * DS + m] * q[Gm::lds(i, j, m)];
+      }
+      if (i == 0) ax += ssq[le][0][c][j + NP * k];
+      if (i == N) ax += ssq[le][1][c][j + NP * k];
+      if (j == 0) ay += ssq[le][2][c][i + NP * k];
+      if (j == N) ay += ssq[le][3][c][i + NP * k];
+      if (k == 0) az += ssq[le][4][c][i + NP * j];
+      if (k == N) az += ssq[le][5][c][i + NP * j];
+      g[3 * c + 0] = sx * ax;
+      g[3 * c + 1] = sy * ay;
+      g[3 * c + 2] = sz * az;
+    }
+  }
   // stress tau_ab (a, b in 0..2), symmetric
   const double dv = (2.0 / 3.0) * (g[0] + g[4] + g[8]);
   double tau[9];
@@ -461,9 +504,9 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
 
 template <int N>
 hipError_t vjp_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
-                 const double* grad, const double* lam, double* gbar, double* ubar, double* out,
+                 const double* lam, double* gbar, double* ubar, double* out,
                  bool acc, double scale, double* cot, double cot_a, double cot_b, hipStream_t s) {
-  hipLaunchKernelGGL((k_vjp_a<N>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U, grad, lam,
+  hipLaunchKernelGGL((k_vjp_a<N>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U, lam,
                      gbar, ubar, m, p, b);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
@@ -479,15 +522,15 @@ hipError_t vjp_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const do
 }  // namespace
 
 hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                          const double* U, const double* grad, const double* lam, double* gbar,
-                          double* ubar, double* out, bool accumulate, double scale,
-                          hipStream_t s, double* cot, double cot_a, double cot_b) {
+                          const double* U, const double* lam, double* gbar, double* ubar,
+                          double* out, bool accumulate, double scale, hipStream_t s, double* cot,
+                          double cot_a, double cot_b) {
   if (m.nE <= 0) return hipSuccess;
   if (cot && !accumulate) return hipErrorInvalidValue;
   switch (N) {
-    case 3: return vjp_n<3>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
-    case 5: return vjp_n<5>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
-    case 7: return vjp_n<7>(m, p, b, U, grad, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
+    case 3: return vjp_n<3>(m, p, b, U, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
+    case 5: return vjp_n<5>(m, p, b, U, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
+    case 7: return vjp_n<7>(m, p, b, U, lam, gbar, ubar, out, accumulate, scale, cot, cot_a, cot_b, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -42,7 +42,7 @@ dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
 
 struct Layout {
   size_t D, w, s[3], status, partial, U0, U1, G, ffv;
-  size_t stages, lamG, lamU, ubar, gbar, agrad, tmp;
+  size_t stages, lamG, lamU, ubar, gbar, tmp;
   size_t fwd_end, adj_end;
 };
 
@@ -74,7 +74,6 @@ Layout layout(const dg_ctx* c) {
   L.lamU = take(state);
   L.ubar = take(state);
   L.gbar = take(12 * dof * sizeof(double));
-  L.agrad = take(12 * dof * sizeof(double));
   L.tmp = take(state);
   L.adj_end = off;
   return L;
@@ -197,11 +196,7 @@ dg_status reverse_stages(dg_ctx* c, In stage_in, double dt, const double* lam_np
                       "axpby kernel")) != DG_OK)
     return st;
   for (int s = 4; s >= 0; --s) {
-    if (c->phys.viscous &&
-        (st = hip_check(c, dg::launch_lift(c->N, m, p, b, stage_in(s), c->agrad, c->stream),
-                        "lift kernel")) != DG_OK)
-      return st;
-    if ((st = hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, stage_in(s), c->agrad, c->lamG, c->gbar,
+    if ((st = hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, stage_in(s), c->lamG, c->gbar,
                                               c->ubar, c->lamU, true, dt, c->stream,
                                               s > 0 ? c->lamG : nullptr, kRkA[s],
                                               s > 0 ? kRkB[s - 1] : 0.0),
@@ -330,10 +325,9 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
     c->lamU = reinterpret_cast<double*>(ws + L.lamU);
     c->ubar = reinterpret_cast<double*>(ws + L.ubar);
     c->gbar = reinterpret_cast<double*>(ws + L.gbar);
-    c->agrad = reinterpret_cast<double*>(ws + L.agrad);
     c->tmp = reinterpret_cast<double*>(ws + L.tmp);
   } else {
-    c->stages = c->lamG = c->lamU = c->ubar = c->tmp = c->gbar = c->agrad = nullptr;
+    c->stages = c->lamG = c->lamU = c->ubar = c->tmp = c->gbar = nullptr;
   }
   c->adjoint_bound = with_adjoint != 0;
   const size_t NP = c->N + 1;
@@ -433,11 +427,8 @@ dg_status dg_eval_rhs_vjp(dg_ctx* c, const double* U, const double* lam, double*
   const dg::DevMesh m = dev_mesh(c);
   const dg::DevPhys p = dev_phys(c);
   const dg::DevBasis b = dev_basis(c);
-  if (c->phys.viscous &&
-      (st = hip_check(c, dg::launch_lift(c->N, m, p, b, U, c->agrad, c->stream), "lift kernel")) != DG_OK)
-    return st;
-  return hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, U, c->agrad, lam, c->gbar, c->ubar, Ubar, false,
-                                         1.0, c->stream),
+  return hip_check(c, dg::launch_rhs_vjp(c->N, m, p, b, U, lam, c->gbar, c->ubar, Ubar, false, 1.0,
+                                         c->stream),
                    "vjp kernels");
 }
 

@@ -66,10 +66,9 @@ hipError_t launch_lift(int N, const DevMesh& m, const DevPhys& p, const DevBasis
 // cot_a cot + cot_b out after out is updated (node by node, fused in the
 // second kernel).
 hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                          const double* U, const double* grad, const double* lam, double* gbar,
-                          double* ubar, double* out, bool accumulate, double scale,
-                          hipStream_t s, double* cot = nullptr, double cot_a = 0.0,
-                          double cot_b = 0.0);
+                          const double* U, const double* lam, double* gbar, double* ubar,
+                          double* out, bool accumulate, double scale, hipStream_t s,
+                          double* cot = nullptr, double cot_a = 0.0, double cot_b = 0.0);
 // y = a y + b x over n doubles.
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
@@ -121,7 +120,6 @@ struct dg_ctx {
   double* lamU = nullptr;
   double* ubar = nullptr;     // per-node partial cotangent of the state
   double* gbar = nullptr;     // cotangent of the lifted gradients
-  double* agrad = nullptr;    // forward lifted gradients of the stage being reversed
   double* tmp = nullptr;      // one state of scratch
 
   // measurement: one event after each timed launch (kernel class 0 = lift, 1 = rhs)
