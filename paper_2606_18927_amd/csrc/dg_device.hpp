@@ -25,10 +25,10 @@ struct Cfg<7> {
   static constexpr int EPB = 1, BS = 512, FACE_WAVES = 8;
 };
 
-template <int N>
+template <int N, int PAD = 1>
 struct Geo {
   static constexpr int NP = N + 1, NF = NP * NP, NN = NF * NP;
-  static constexpr int RS = NP + 1;        // padded x-row stride of an LDS block
+  static constexpr int RS = NP + PAD;      // x-row stride of an LDS block
   static constexpr int EB = RS * NP * NP;  // LDS entries per element and field
   static constexpr int DS = NP + 1;        // padded row stride of D in LDS
   __device__ static constexpr int lds(int i, int j, int k) { return i + RS * (j + NP * k); }
