@@ -41,11 +41,23 @@
 namespace dg {
 namespace {
 
-// Line sums along direction d of four LDS fields q0..q3 at node (i, j, k);
-// D is read once per line position.
-template <int N, typename R, int d>
-__device__ inline void line_sums4(const R* sD, const R* q0, const R* q1, const R* q2, const R* q3,
-                                  int i, int j, int k, R a[4]) {
+// Vector of two R values (one 64- or 128-bit LDS access).
+template <typename R>
+struct V2T;
+template <>
+struct V2T<double> {
+  using type = double2;
+};
+template <>
+struct V2T<float> {
+  using type = float2;
+};
+
+// Line sums along direction d of (u, v, w, T) held as LDS pairs q[0] = (u, v),
+// q[1] = (w, T) at node (i, j, k); D is read once per line position.
+template <int N, typename R, int d, typename V2>
+__device__ inline void line_sums_pairs(const R* sD, const V2 (*q)[Geo<N>::EB], int i, int j, int k,
+                                       R a[4]) {
   using Gm = Geo<N>;
   constexpr int NP = Gm::NP;
   const int idx = d == 0 ? i : (d == 1 ? j : k);
@@ -54,36 +66,37 @@ __device__ inline void line_sums4(const R* sD, const R* q0, const R* q1, const R
   for (int m = 0; m < NP; ++m) {
     const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
     const R Dm = sD[idx * Gm::DS + m];
-    a[0] += Dm * q0[lm];
-    a[1] += Dm * q1[lm];
-    a[2] += Dm * q2[lm];
-    a[3] += Dm * q3[lm];
+    const V2 uv = q[0][lm], wT = q[1][lm];
+    a[0] += Dm * uv.x;
+    a[1] += Dm * uv.y;
+    a[2] += Dm * wT.x;
+    a[3] += Dm * wT.y;
   }
 }
 
-// BR1 lifted gradients g[3 q + d] of the four LDS fields q0..q3 at node
+// BR1 lifted gradients g[3 q + d] of (u, v, w, T) (LDS pairs) at node
 // (i, j, k), with the lifting corrections ssq of the six faces.
-template <int N, typename R>
-__device__ inline void lifted_gradients(const R* sD, const R* q0, const R* q1, const R* q2,
-                                        const R* q3, const R (*ssq)[4][Geo<N>::NF], int i, int j,
-                                        int k, R sx, R sy, R sz, R g[12]) {
+template <int N, typename R, typename V2>
+__device__ inline void lifted_gradients(const R* sD, const V2 (*q)[Geo<N>::EB],
+                                        const R (*ssq)[4][Geo<N>::NF], int i, int j, int k, R sx,
+                                        R sy, R sz, R g[12]) {
   constexpr int NP = N + 1;
   R a[4];
-  line_sums4<N, R, 0>(sD, q0, q1, q2, q3, i, j, k, a);
+  line_sums_pairs<N, R, 0, V2>(sD, q, i, j, k, a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (i == 0) a[c] += ssq[0][c][j + NP * k];
     if (i == N) a[c] += ssq[1][c][j + NP * k];
     g[3 * c + 0] = sx * a[c];
   }
-  line_sums4<N, R, 1>(sD, q0, q1, q2, q3, i, j, k, a);
+  line_sums_pairs<N, R, 1, V2>(sD, q, i, j, k, a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (j == 0) a[c] += ssq[2][c][i + NP * k];
     if (j == N) a[c] += ssq[3][c][i + NP * k];
     g[3 * c + 1] = sy * a[c];
   }
-  line_sums4<N, R, 2>(sD, q0, q1, q2, q3, i, j, k, a);
+  line_sums_pairs<N, R, 2, V2>(sD, q, i, j, k, a);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     if (k == 0) a[c] += ssq[4][c][i + NP * j];
@@ -194,8 +207,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
   constexpr int NFN = n_face_nodes<N>();
   static_assert(EPB * NFN <= BS, "one lane per face node");
+  using V2 = typename V2T<R>::type;
   __shared__ R sD[NP * Gm::DS];
-  __shared__ R sq[EPB][4][EB];
+  __shared__ V2 sq[EPB][2][EB];  // (u, v), (w, T - T_ref)
   __shared__ R ssq[EPB][6][4][NF];
 
   const int tid = threadIdx.x;
@@ -254,10 +268,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     double p_ref, e_ref, T_ref;
     element_ref<R>(s0, ph, p_ref, e_ref, T_ref);
     const int l = Gm::lds(i, j, k);
-    sq[nle][0][l] = static_cast<R>(P.u);
-    sq[nle][1][l] = static_cast<R>(P.v);
-    sq[nle][2][l] = static_cast<R>(P.w);
-    sq[nle][3][l] = static_cast<R>(P.T - T_ref);
+    sq[nle][0][l] = V2{static_cast<R>(P.u), static_cast<R>(P.v)};
+    sq[nle][1][l] = V2{static_cast<R>(P.w), static_cast<R>(P.T - T_ref)};
   }
   if (tid < NP * NP) sD[(tid / NP) * Gm::DS + tid % NP] = static_cast<R>(dval);
   __syncthreads();
@@ -265,7 +277,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     if (face_ok) {
       const FaceTask<N> ft(tid);
       const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
-      const double qo[4] = {sq[ft.le][0][lo], sq[ft.le][1][lo], sq[ft.le][2][lo], sq[ft.le][3][lo]};
+      const V2 uv = sq[ft.le][0][lo], wT = sq[ft.le][1][lo];
+      const double qo[4] = {uv.x, uv.y, wT.x, wT.y};
       double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
       if (!fwall) {
         const Prim Pn = primitives(sn, ph);
@@ -291,12 +304,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     int ex = ex0, ey = ey0, ez = ez0;
     if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
     R g[12];
-    lifted_gradients<N, R>(sD, sq[le][0], sq[le][1], sq[le][2], sq[le][3], ssq[le], i, j, k,
-                           static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
-                           static_cast<R>(mesh.s[2][ez]), g);
+    lifted_gradients<N, R, V2>(sD, sq[le], ssq[le], i, j, k, static_cast<R>(mesh.s[0][ex]),
+                               static_cast<R>(mesh.s[1][ey]), static_cast<R>(mesh.s[2][ez]), g);
     const R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
     const int l = Gm::lds(i, j, k);
-    const R u = sq[le][0][l], v = sq[le][1][l], w = sq[le][2][l];
+    const V2 uv = sq[le][0][l], wT = sq[le][1][l];
+    const R u = uv.x, v = uv.y, w = wT.x;
     R* out = ffv + e * (6 * 4 * NF);
     R f[4];
     if (i == 0 || i == N) {
@@ -330,18 +343,6 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
 // ring lanes need.
 template <int N>
 using GeoR = Geo<N, 0>;
-
-// Vector of two R values (one 64- or 128-bit LDS access).
-template <typename R>
-struct V2T;
-template <>
-struct V2T<double> {
-  using type = double2;
-};
-template <>
-struct V2T<float> {
-  using type = float2;
-};
 
 // Line sums of direction d at node (i, j, k): ac = sum_m D_im f#_KG(own, m),
 // av = sum_m D_im f_v,d(m), du = sum_m D_im u_d,m / 2 (mixed-precision add-back).
