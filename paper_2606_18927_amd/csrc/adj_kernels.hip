@@ -180,10 +180,12 @@ __device__ inline double nb_scale(const DevMesh& m, int ex, int ey, int ez, int 
 // --------------------------------------------------------------------------
 // k_vjp_a
 // --------------------------------------------------------------------------
-// Bounded for two waves per SIMD: without the bound the degree-5 kernel takes a
-// few registers over 256 and runs one wave per SIMD.
+// The line loops of the volume cotangents stay rolled and the kernel is
+// bounded for four waves per SIMD: unrolled, each iteration's LDS operands
+// are hoisted and the kernel needs all 256 registers (two waves per SIMD,
+// 15 % slower at degree 5).
 template <int N>
-__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2))) void k_vjp_a(const double* __restrict__ U,
+__global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_vjp_a(const double* __restrict__ U,
                                                        const double* __restrict__ lam,
                                                        double* __restrict__ gbar,
                                                        double* __restrict__ ubar, DevMesh mesh,
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(2)))
     const int ab = D == 0 ? j + NP * k : (D == 1 ? i + NP * k : i + NP * j);                   \
     const double sd = mesh.s[D][D == 0 ? ex : (D == 1 ? ey : ez)];                              \
     double Fv[4] = {0, 0, 0, 0};                                                               \
-    _Pragma("unroll") for (int m = 0; m < NP; ++m) {                                           \
+    _Pragma("unroll 1") for (int m = 0; m < NP; ++m) {                                         \
       const int lm = D == 0 ? Gm::lds(m, j, k) : (D == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m)); \
       const double Dim = sD[idx * DS + m], Dmi = sD[m * DS + idx];                              \
       double b[6], lmv[5], mu5[5];                                                             \
