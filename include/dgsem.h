@@ -164,6 +164,28 @@ dg_status dg_rk_record_stages(dg_ctx* ctx, const double* U0_dev, double t, doubl
 dg_status dg_rk_step_vjp_stages(dg_ctx* ctx, const double* stages_dev, double t, double dt,
                                 const double* lamU_np1_dev, double* lamU_n_dev);
 
+/* Wall faces of the mesh: 2 nb nc for every direction whose ends are walls
+ * (nb, nc the element counts of the other two directions).  Host only.      */
+dg_status dg_wall_faces(const dg_ctx* ctx, long long* n_faces);
+
+/* Algebraic equilibrium wall-stress model (paper Sec. 3, one GPU lane per
+ * wall-face node): at each node of each wall face, the state at the LGL node
+ * n_wm (1..N, counted from the wall) of the wall-normal line through it, a
+ * distance h_wm = (xi_nwm + 1) width / 2 from the wall; the wall-parallel
+ * velocity u_par (normal component removed) and its direction t; the Van
+ * Driest transform for an adiabatic wall, u_VD = a asin(u_par / a),
+ * a^2 = 2 c_p T_w / r, T_w = T + r u_par^2 / (2 c_p), r = Pr^(1/3); wall
+ * density p / (R T_w) and viscosity mu; u_tau from Spalding's law
+ * h u_tau / nu_w = f(u_VD / u_tau), f(u+) = u+ + 0.1108 (exp(0.4 u+) - 1 -
+ * 0.4 u+ - (0.4 u+)^2/2 - (0.4 u+)^3/6 - (0.4 u+)^4/24) (Newton, from below).
+ * Writes tau_dev[(face 3 + c) (N+1)^2 + a + (N+1) b] = rho_w u_tau^2 t_c for
+ * the dg_wall_faces faces in order: wall directions x, y, z; lower then upper
+ * wall; wall elements with the first remaining element index fastest; face
+ * nodes (a, b) = (j, k), (i, k), (i, j) for walls normal to x, y, z.
+ * Errors: DG_EINVAL (null pointers, n_wm outside 1..N), DG_ESTATE (no
+ * workspace).  Zero faces (no walls) is a no-op.                            */
+dg_status dg_wall_stress(dg_ctx* ctx, const double* U_dev, int n_wm, double* tau_dev);
+
 /* Volume-averaged kinetic energy J(U) = sum wJ |m|^2/(2 rho) / sum wJ with LGL
  * quadrature, written to J_dev[0] (device double).                           */
 dg_status dg_kinetic_energy(dg_ctx* ctx, const double* U_dev, double* J_dev);

@@ -484,6 +484,24 @@ dg_status dg_rk_step_vjp_stages(dg_ctx* c, const double* stages, double /*t*/, d
   return reverse_stages(c, [&](int s) { return stages + static_cast<size_t>(s) * n5; }, dt, lam_np1, lam_n);
 }
 
+dg_status dg_wall_faces(const dg_ctx* c, long long* n) {
+  if (!c || !n) return DG_EINVAL;
+  *n = dg::wall_faces(dev_mesh(c));
+  return DG_OK;
+}
+
+dg_status dg_wall_stress(dg_ctx* c, const double* U, int n_wm, double* tau) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (n_wm < 1 || n_wm > c->N) return fail(c, DG_EINVAL, "interface node index outside 1..N");
+  if (dg::wall_faces(dev_mesh(c)) == 0) return DG_OK;  // no walls: nothing to write
+  if (!U || !tau) return fail(c, DG_EINVAL, "bad pointers");
+  const double recovery = std::cbrt(c->phys.Pr);
+  return hip_check(c, dg::launch_wall_stress(c->N, dev_mesh(c), dev_phys(c), U, n_wm, c->xi[n_wm] + 1.0,
+                                             recovery, tau, c->stream),
+                   "wall stress kernel");
+}
+
 dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double* J) {
   dg_status st = need_bound(c);
   if (st != DG_OK) return st;

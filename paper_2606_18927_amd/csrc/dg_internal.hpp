@@ -72,6 +72,12 @@ hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBa
 // y = a y + b x over n doubles.
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
+// Wall-stress model: number of wall faces of the mesh, and the kernel (one
+// lane per wall-face node).
+long long wall_faces(const DevMesh& m);
+hipError_t launch_wall_stress(int N, const DevMesh& m, const DevPhys& p, const double* U, int n_wm,
+                              double xi_wm1, double recovery, double* tau, hipStream_t s);
+
 // Reductions and elementwise kernels (aux_kernels.hip).
 hipError_t launch_kinetic_energy(int N, const DevMesh& m, const double* w, const double* U,
                                  double* partial, int n_partial, double inv_vol, double* J,

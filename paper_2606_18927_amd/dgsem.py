@@ -65,6 +65,8 @@ _SIGNATURES = {
     "dg_rk_step_vjp": (_I, [_P, _P, _D, _D, _P, _P]),
     "dg_rk_record_stages": (_I, [_P, _P, _D, _D, _I, _P]),
     "dg_rk_step_vjp_stages": (_I, [_P, _P, _D, _D, _P, _P]),
+    "dg_wall_faces": (_I, [_P, ctypes.POINTER(ctypes.c_longlong)]),
+    "dg_wall_stress": (_I, [_P, _P, _I, _P]),
     "dg_kinetic_energy": (_I, [_P, _P, _P]),
     "dg_kinetic_energy_grad": (_I, [_P, _P, _P]),
     "dg_stream_triad": (_I, [_P, _P, _D, _P, ctypes.c_longlong, _P]),
@@ -251,6 +253,20 @@ class Solver:
                                                 self._state_ptr(out, "lam_n")),
                     "dg_rk_step_vjp_stages")
         return out
+
+    def wall_faces(self) -> int:
+        n = ctypes.c_longlong()
+        self._check(lib().dg_wall_faces(self._ctx, ctypes.byref(n)), "dg_wall_faces")
+        return n.value
+
+    def wall_stress(self, U: torch.Tensor, n_wm: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Wall-stress vectors (wall_faces, 3, (N+1)^2) of the algebraic wall model."""
+        NP = self.mesh.N + 1
+        n = self.wall_faces() * 3 * NP * NP
+        out = torch.empty(n, dtype=torch.float64, device=self.device) if out is None else out
+        self._check(lib().dg_wall_stress(self._ctx, self._state_ptr(U), int(n_wm), _ptr(out, n, "tau")),
+                    "dg_wall_stress")
+        return out.view(-1, 3, NP * NP)
 
     def kinetic_energy(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         out = torch.empty(1, dtype=torch.float64, device=self.device) if out is None else out

@@ -131,3 +131,16 @@ def test_workspace_size_and_state_errors(L):
     L.dg_workspace_bytes(ctx, 0, ctypes.byref(mixed))
     assert fwd.value - mixed.value >= 3 * dof * 4 - 4096
     L.dg_free(ctx)
+
+
+def test_wall_face_count(L):
+    """dg_wall_faces is host-only: 2 nb nc per wall direction."""
+    n = ctypes.c_longlong()
+    for bc, expected in (((0, 0, 0), 0), ((0, 1, 0), 2 * 3 * 5), ((1, 1, 1), 2 * (2 * 5 + 3 * 5 + 3 * 2))):
+        d, keep = _desc(n=(3, 2, 5), bc=bc)
+        st, ctx = _init(L, d, _phys())
+        assert st == dgsem.DG_OK
+        assert L.dg_wall_faces(ctx, ctypes.byref(n)) == dgsem.DG_OK and n.value == expected
+        # device call without a workspace is refused before any HIP call
+        assert L.dg_wall_stress(ctx, None, 1, None) == dgsem.DG_ESTATE
+        L.dg_free(ctx)
