@@ -47,7 +47,7 @@ from fractions import Fraction
 import torch
 
 from .basis import diff_matrix, lgl
-from .mesh import ELEM_AXIS, NODE_AXIS, WALL, Mesh
+from .mesh import ELEM_AXIS, NODE_AXIS, WALL, WALL_MODEL, Mesh
 from .physics import (FLUXES, Gas, Prim, ec_flux, euler_flux, kg_flux, llf_flux, primitives,
                       roe_flux, viscous_flux, wall_convective_flux)
 
@@ -109,6 +109,23 @@ def _end_mask(plane: torch.Tensor, ea: int, last: bool) -> torch.Tensor:
     return m.reshape(shape)
 
 
+def _wall_plane(t: torch.Tensor, like: torch.Tensor, d: int, ea: int) -> torch.Tensor:
+    """Wall-face values t[eb, ea, b, a] (face nodes (a, b) = (j, k), (i, k), (i, j)
+    and wall elements (ea, eb) = (ey, ez), (ex, ez), (ex, ey) for d = x, y, z)
+    placed on a face plane shaped like `like`: (nz, ny, nx, ...) without the
+    direction-d element and node axes selected, broadcast along the d element axis."""
+    # the plane tensors keep the element axes (nz, ny, nx) and two node axes
+    # ordered (k, j, i) without the d one; e.g. d = 1: (nz, ny, nx, k, i)
+    out = torch.zeros_like(like)
+    if d == 0:      # like: (nz, ny, nx, k, j); t[ez, ey, k, j]
+        val = t.permute(0, 1, 2, 3)[:, :, None, :, :]
+    elif d == 1:    # like: (nz, ny, nx, k, i); t[ez, ex, k, i]
+        val = t[:, None, :, :, :]
+    else:           # like: (nz, ny, nx, j, i); t[ey, ex, j, i]
+        val = t[None, :, :, :, :]
+    return out + val
+
+
 def _prim_plane(P: Prim, na: int, idx: int) -> Prim:
     s = lambda x: x.select(na, idx)  # noqa: E731
     return Prim(s(P.rho), tuple(s(x) for x in P.vel), s(P.p), s(P.T), s(P.e), s(P.E))
@@ -150,6 +167,12 @@ def lift(U: torch.Tensor, mesh: Mesh, gas: Gas):
                 wv = torch.full_like(lo, q_wall[c])
                 star_lo = torch.where(_end_mask(lo, ea, last=False), wv, star_lo)
                 star_hi = torch.where(_end_mask(hi, ea, last=True), wv, star_hi)
+            elif mesh.bc[d] == WALL_MODEL:
+                # slip, adiabatic wall: the own value with the normal velocity removed
+                wlo = torch.zeros_like(lo) if c == d else lo
+                whi = torch.zeros_like(hi) if c == d else hi
+                star_lo = torch.where(_end_mask(lo, ea, last=False), wlo, star_lo)
+                star_hi = torch.where(_end_mask(hi, ea, last=True), whi, star_hi)
             surf = (_at_node(star_hi - hi, na, N, NP) / w[N]
                     - _at_node(star_lo - lo, na, 0, NP) / w[0])
             grad[c][d] = s * (vol + surf)
@@ -208,6 +231,42 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
         # the lower face of an element is the upper face of its lower neighbour
         F_lo = [torch.roll(F_hi[v], 1, ea) for v in range(5)]
 
+        if mesh.bc[d] == WALL_MODEL:
+            # slip, adiabatic wall: pressure-only convective flux; viscous flux
+            # with the modelled wall shear stress (sign: the stress on the fluid
+            # below an upper wall is the negative), the own normal viscous stress,
+            # and no energy flux (adiabatic, stationary wall)
+            from .wallmodel import wall_stress_field
+            tau = torch.as_tensor(wall_stress_field(U, mesh, gas, mesh.wm_node, lambda T: gas.mu))
+            wall_index = [dd for dd in range(3) if mesh.bc[dd] != "periodic"]
+            base = 0
+            for dd in wall_index:
+                if dd == d:
+                    break
+                others = [c for c in range(3) if c != dd]
+                base += 2 * mesh.nelem[others[0]] * mesh.nelem[others[1]]
+            others = [c for c in range(3) if c != d]
+            na_e, nb_e = mesh.nelem[others[0]], mesh.nelem[others[1]]
+            for plane_P, idx, F, last in ((P_lo, 0, F_lo, False), (P_hi, N, F_hi, True)):
+                side = 1 if last else 0
+                # (faces, 3, NP, NP) of this wall, face index = ea + na_e eb, node (a, b)
+                t = tau[base + side * na_e * nb_e: base + (side + 1) * na_e * nb_e].reshape(nb_e, na_e, 3, NP, NP)
+                sgn = -1.0 if last else 1.0
+                fwc = wall_convective_flux(plane_P, d)
+                if viscous:
+                    g_plane = [[grad[c][b].select(na, idx) for b in range(3)] for c in range(4)]
+                    fvo = viscous_flux(plane_P.vel, g_plane, d, gas)
+                fwv = [torch.zeros_like(plane_P.p) for _ in range(5)]
+                for c in range(3):
+                    if not viscous:
+                        continue
+                    if c == d:
+                        fwv[1 + c] = fvo[1 + c]
+                    else:
+                        fwv[1 + c] = sgn * _wall_plane(t[:, :, c], plane_P.p, d, ea)
+                mask = _end_mask(plane_P.p, ea, last)
+                for v in range(5):
+                    F[v] = torch.where(mask, fwc[v] - fwv[v], F[v])
         if mesh.bc[d] == WALL:
             zero = torch.zeros_like(U[0])
             for plane_P, idx, F, last in ((P_lo, 0, F_lo, False), (P_hi, N, F_hi, True)):

@@ -7,8 +7,9 @@ J_e = dx dy dz / 8 and the metric scale along direction d is s_d = 2 / d_d
 (paper Sec. 2: the operator is applied per hexahedral element; Sec. 3/4 use
 periodic and wall boundaries).
 
-Each direction is either periodic or closed by an isothermal no-slip wall at
-both ends (the wall reading is stated in ``physics``).
+Each direction is periodic or closed at both ends by an isothermal no-slip
+wall or by a slip, adiabatic wall whose shear stress comes from the wall-stress
+model (the wall readings are stated in ``physics`` and ``dgsem``).
 
 Tensor layout used throughout the oracle: a nodal field is a tensor of shape
 (nz, ny, nx, N+1, N+1, N+1) indexed [ez, ey, ex, k, j, i]; this is the row-major
@@ -25,7 +26,8 @@ import torch
 
 from .basis import lgl
 
-__all__ = ["Mesh", "ELEM_AXIS", "NODE_AXIS", "uniform_faces", "tanh_faces"]
+__all__ = ["Mesh", "ELEM_AXIS", "NODE_AXIS", "uniform_faces", "tanh_faces", "PERIODIC", "WALL",
+           "WALL_MODEL"]
 
 # axis of a nodal field (nz, ny, nx, k, j, i) that runs along direction d
 ELEM_AXIS = (2, 1, 0)
@@ -33,6 +35,7 @@ NODE_AXIS = (5, 4, 3)
 
 PERIODIC = "periodic"
 WALL = "wall"
+WALL_MODEL = "wallmodel"  # slip, adiabatic wall with the wall-stress model (``wallmodel``)
 
 
 def uniform_faces(n: int, lo: float, hi: float) -> np.ndarray:
@@ -51,6 +54,7 @@ class Mesh:
     faces: tuple  # three 1-D float64 arrays (x, y, z face coordinates)
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
     T_wall: float = 1.0
+    wm_node: int = 1  # interface LGL node (from the wall) of WALL_MODEL ends
 
     def __post_init__(self):
         self.faces = tuple(np.asarray(f, dtype=np.float64) for f in self.faces)
@@ -58,7 +62,7 @@ class Mesh:
             if f.ndim != 1 or f.size < 2 or np.any(np.diff(f) <= 0):
                 raise ValueError("face coordinates must be strictly increasing")
         for b in self.bc:
-            if b not in (PERIODIC, WALL):
+            if b not in (PERIODIC, WALL, WALL_MODEL):
                 raise ValueError(f"unknown boundary kind {b!r}")
 
     @property

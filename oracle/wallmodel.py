@@ -121,7 +121,7 @@ def wall_stress_field(U, mesh, gas: Gas, n_wm: int, mu_of_T) -> np.ndarray:
     other two element indices fastest; face nodes (a, b) = (j, k), (i, k), (i, j)
     for d = x, y, z, a fastest."""
     from .basis import lgl
-    from .mesh import WALL
+    from .mesh import PERIODIC
     from .physics import primitives
     N, NP = mesh.N, mesh.N + 1
     xi, _ = lgl(N)
@@ -132,7 +132,7 @@ def wall_stress_field(U, mesh, gas: Gas, n_wm: int, mu_of_T) -> np.ndarray:
     nel = mesh.nelem  # (nx, ny, nz)
     out = []
     for d in range(3):
-        if mesh.bc[d] != WALL:
+        if mesh.bc[d] == PERIODIC:
             continue
         others = [c for c in range(3) if c != d]
         width = np.diff(np.asarray(mesh.faces[d], dtype=np.float64))
