@@ -49,6 +49,9 @@ typedef enum {
 
 #define DG_BC_PERIODIC 0
 #define DG_BC_ISOTHERMAL_WALL 1
+#define DG_BC_WALL_MODEL 2   /* slip, adiabatic wall whose shear stress comes from the
+                                algebraic wall model (dg_wall_stress) evaluated on the
+                                state of every stage; FP64 only; no adjoint           */
 
 #define DG_FP64 0
 #define DG_MIXED 1
@@ -74,6 +77,8 @@ typedef struct {
   const double* faces[3];
   int bc[3];
   double T_wall;      /* wall temperature of DG_BC_ISOTHERMAL_WALL ends          */
+  int wm_node;        /* interface LGL node (1..N, from the wall) of the wall model
+                         at DG_BC_WALL_MODEL ends; ignored otherwise            */
 } dg_mesh_desc;
 
 /* Gas and scheme switches.  Viscosity is constant; the heat conductivity is

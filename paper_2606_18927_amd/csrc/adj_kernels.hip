@@ -255,7 +255,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
         // forward lifting correction (q* - q_own) (+-1/w_end) of this face node
         const Prim Po = primitives(so, ph);
         const double qo[4] = {Po.u, Po.v, Po.w, Po.T};
-        double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+        double qs[4];
+        wall_lifting_value(mesh, ft.d, qo, qs);
         if (!wall) {
           const Prim Pn = primitives(sn, ph);
           qs[0] = 0.5 * (qo[0] + Pn.u);

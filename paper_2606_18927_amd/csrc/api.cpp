@@ -41,7 +41,7 @@ dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 struct Layout {
-  size_t D, w, s[3], status, partial, U0, U1, G, ffv;
+  size_t D, w, s[3], status, partial, U0, U1, G, ffv, tauw;
   size_t stages, lamG, lamU, ubar, gbar, tmp;
   size_t fwd_end, adj_end;
 };
@@ -68,6 +68,7 @@ Layout layout(const dg_ctx* c) {
   L.U1 = take(state);
   L.G = take(state);
   L.ffv = c->phys.viscous ? take(fbytes) : off;
+  L.tauw = c->wall_model ? take(static_cast<size_t>(c->n_wall_faces) * 3 * NP * NP * sizeof(double)) : off;
   L.fwd_end = off;
   L.stages = take(5 * state);
   L.lamG = take(state);
@@ -88,6 +89,7 @@ dg::DevMesh dev_mesh(const dg_ctx* c) {
   }
   m.T_wall = c->T_wall;
   m.nE = c->nE;
+  m.tauw = c->wall_model ? c->tauw : nullptr;
   return m;
 }
 
@@ -134,6 +136,16 @@ dg_status need_bound(dg_ctx* c) {
   return DG_OK;
 }
 
+// The wall model's stress of state U at DG_BC_WALL_MODEL walls, for the
+// right-hand side of U (no-op without such walls or viscosity).
+dg_status wall_model_stress(dg_ctx* c, const double* U) {
+  if (!c->wall_model || !c->phys.viscous) return DG_OK;
+  return hip_check(c, dg::launch_wall_stress(c->N, dev_mesh(c), dev_phys(c), U, c->wm_node,
+                                             c->xi[c->wm_node] + 1.0, std::cbrt(c->phys.Pr), c->tauw,
+                                             c->stream),
+                   "wall stress kernel");
+}
+
 // Lifting (if viscous) then the right-hand side of U into Ut.
 dg_status eval_rhs_into(dg_ctx* c, const double* U, double* Ut) {
   const dg::DevMesh m = dev_mesh(c);
@@ -145,6 +157,7 @@ dg_status eval_rhs_into(dg_ctx* c, const double* U, double* Ut) {
     if (st != DG_OK) return st;
     mark(c, 0);
   }
+  if (dg_status st = wall_model_stress(c, U); st != DG_OK) return st;
   dg_status st = hip_check(c, dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->ffv, Ut, c->dstatus,
                                              c->stream),
                            "rhs kernel");
@@ -166,6 +179,7 @@ dg_status forward_stages(dg_ctx* c, const double* in, double dt, Out stage_out) 
         (st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, cur, c->ffv, c->stream),
                         "face flux kernel")) != DG_OK)
       return st;
+    if ((st = wall_model_stress(c, cur)) != DG_OK) return st;
     const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
     double* out = stage_out(s);
     if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, cur, c->ffv, c->G, out,
@@ -213,6 +227,7 @@ dg_status need_adjoint(dg_ctx* c) {
   if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
   if (c->phys.flux != DG_FLUX_KG_LLF)
     return fail(c, DG_EUNSUPPORTED, "the adjoint is built for the Kennedy-Gruber / Lax-Friedrichs fluxes");
+  if (c->wall_model) return fail(c, DG_EUNSUPPORTED, "the adjoint does not cover the wall model");
   return DG_OK;
 }
 
@@ -239,7 +254,9 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   long long nE = 1;
   for (int d = 0; d < 3; ++d) {
     if (mesh->nelem[d] <= 0 || !mesh->faces[d]) return DG_EINVAL;
-    if (mesh->bc[d] != DG_BC_PERIODIC && mesh->bc[d] != DG_BC_ISOTHERMAL_WALL) return DG_EINVAL;
+    if (mesh->bc[d] != DG_BC_PERIODIC && mesh->bc[d] != DG_BC_ISOTHERMAL_WALL &&
+        mesh->bc[d] != DG_BC_WALL_MODEL)
+      return DG_EINVAL;
     for (int i = 0; i < mesh->nelem[d]; ++i) {
       const double a = mesh->faces[d][i], b = mesh->faces[d][i + 1];
       if (!(b > a) || !std::isfinite(a) || !std::isfinite(b)) return DG_EINVAL;
@@ -255,6 +272,10 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
     return DG_EINVAL;
   if (phys->flux != DG_FLUX_KG_LLF && phys->flux != DG_FLUX_EC_ROE) return DG_EINVAL;
   if (phys->flux == DG_FLUX_EC_ROE && phys->precision != DG_FP64) return DG_EUNSUPPORTED;
+  const bool wall_model = mesh->bc[0] == DG_BC_WALL_MODEL || mesh->bc[1] == DG_BC_WALL_MODEL ||
+                          mesh->bc[2] == DG_BC_WALL_MODEL;
+  if (wall_model && (mesh->wm_node < 1 || mesh->wm_node > mesh->N)) return DG_EINVAL;
+  if (wall_model && phys->precision != DG_FP64) return DG_EUNSUPPORTED;
   if (mesh->bc[0] == DG_BC_ISOTHERMAL_WALL || mesh->bc[1] == DG_BC_ISOTHERMAL_WALL ||
       mesh->bc[2] == DG_BC_ISOTHERMAL_WALL) {
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;
@@ -272,6 +293,8 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
       c->s[d][i] = 2.0 / (c->faces[d][i + 1] - c->faces[d][i]);
   }
   c->T_wall = mesh->T_wall;
+  c->wall_model = wall_model;
+  c->wm_node = mesh->wm_node;
   c->phys = *phys;
   c->phys.viscous = phys->viscous ? 1 : 0;
   c->phys.central_only = phys->central_only ? 1 : 0;
@@ -279,6 +302,7 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   c->nE = nE;
   c->nn = nn;
   c->n_dof = nE * nn;
+  c->n_wall_faces = dg::wall_faces(dev_mesh(c));
   dg::lgl_nodes_weights(c->N, c->xi, c->w);
   dg::lgl_diff_matrix(c->xi, c->D);
   *out = c;
@@ -319,6 +343,7 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
   c->cur = 0;
   c->G = reinterpret_cast<double*>(ws + L.G);
   c->ffv = c->phys.viscous ? static_cast<void*>(ws + L.ffv) : nullptr;
+  c->tauw = c->wall_model ? reinterpret_cast<double*>(ws + L.tauw) : nullptr;
   if (with_adjoint) {
     c->stages = reinterpret_cast<double*>(ws + L.stages);
     c->lamG = reinterpret_cast<double*>(ws + L.lamG);
@@ -408,6 +433,7 @@ dg_status dg_rk_step(dg_ctx* c, double /*t*/, double dt, int nsteps) {
           return st;
         mark(c, 0);
       }
+      if ((st = wall_model_stress(c, Uin)) != DG_OK) return st;
       const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
       if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, Uin, c->ffv, c->G,
                                                  Uout, stage, c->dstatus, c->stream),

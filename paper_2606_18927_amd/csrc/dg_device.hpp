@@ -83,6 +83,39 @@ __device__ inline long long neighbour(const DevMesh& m, int ex, int ey, int ez, 
   return static_cast<long long>(x + m.n[0] * (y + m.n[1] * z));
 }
 
+// BR1 lifting value q* of q = (u, v, w, T) at a wall normal to d: the
+// isothermal no-slip wall imposes (0, 0, 0, T_wall); the slip, adiabatic wall
+// of the wall model keeps the own values qo with the normal velocity removed.
+__device__ inline void wall_lifting_value(const DevMesh& m, int d, const double qo[4], double qs[4]) {
+  if (pick3(m.bc[0], m.bc[1], m.bc[2], d) == DG_BC_WALL_MODEL) {
+    qs[0] = d == 0 ? 0.0 : qo[0];
+    qs[1] = d == 1 ? 0.0 : qo[1];
+    qs[2] = d == 2 ? 0.0 : qo[2];
+    qs[3] = qo[3];
+  } else {
+    qs[0] = qs[1] = qs[2] = 0.0;
+    qs[3] = m.T_wall;
+  }
+}
+
+// Index of the wall face of element (ex, ey, ez) on its lower (up = false) or
+// upper wall normal to d, in the order of the wall-stress output: wall
+// directions x, y, z; lower then upper wall; the wall elements with the first
+// remaining element index fastest.
+__device__ inline long long wall_face_index(const DevMesh& m, int ex, int ey, int ez, int d, bool up) {
+  long long base = 0;
+#pragma unroll
+  for (int dd = 0; dd < 3; ++dd) {
+    if (dd < d && m.bc[dd] != DG_BC_PERIODIC) {
+      const long long na = dd == 0 ? m.n[1] : m.n[0], nb = dd == 2 ? m.n[1] : m.n[2];
+      base += 2 * na * nb;
+    }
+  }
+  const long long na = pick3(m.n[1], m.n[0], m.n[0], d), nb = pick3(m.n[2], m.n[2], m.n[1], d);
+  const long long ea = d == 0 ? ey : ex, eb = d == 2 ? ey : ez;
+  return base + (up ? na * nb : 0) + ea + na * eb;
+}
+
 // Node (i, j, k) of face f = 2 d + up with in-face coordinates (a, b):
 // d = 0: (i, j, k) = (n, a, b); d = 1: (a, n, b); d = 2: (a, b, n), n = 0 or N.
 template <int N>

@@ -22,6 +22,7 @@ struct DevMesh {
   double T_wall;
   const double* s[3]; // device tables of s_d per element index along d
   long long nE;       // number of elements
+  const double* tauw; // wall-model stress per wall-face node (DG_BC_WALL_MODEL), or null
 };
 
 // Gas constants and switches (FP64; kernels cast where they compute in FP32).
@@ -99,6 +100,10 @@ struct dg_ctx {
   std::vector<double> faces[3];
   int bc[3] = {0, 0, 0};
   double T_wall = 1.0;
+  int wm_node = 1;            // interface node of the wall model
+  bool wall_model = false;    // some direction has DG_BC_WALL_MODEL ends
+  double* tauw = nullptr;     // wall stress of the current stage (workspace)
+  long long n_wall_faces = 0;
   dg_physics phys{};
   hipStream_t stream = nullptr;
   long long nE = 0, nn = 0, n_dof = 0;

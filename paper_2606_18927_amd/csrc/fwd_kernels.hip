@@ -279,7 +279,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
       const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
       const V2 uv = sq[ft.le][0][lo], wT = sq[ft.le][1][lo];
       const double qo[4] = {uv.x, uv.y, wT.x, wT.y};
-      double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+      double qs[4];
+      wall_lifting_value(mesh, ft.d, qo, qs);
       if (!fwall) {
         const Prim Pn = primitives(sn, ph);
         qs[0] = 0.5 * (qo[0] + Pn.u);
@@ -846,7 +847,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       const V2 ru = sp[ft.le][0][lo], vw = sp[ft.le][1][lo];
       constexpr double hv = EC ? 1.0 : 2.0;  // sp holds halves unless EC
       const double qo[4] = {hv * ru.y, hv * vw.x, hv * vw.y, sTf[lo]};
-      double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+      double qs[4];
+      wall_lifting_value(mesh, ft.d, qo, qs);
       if (!fwall) {
         const Prim Pn = primitives(sn, ph);
         qs[0] = 0.5 * (qo[0] + Pn.u);
@@ -974,6 +976,21 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
       for (int c = 0; c < 4; ++c) fvo[c] = static_cast<double>(sX[ft.le][ft.f][c][ft.ab]);
     }
+    // slip, adiabatic wall of the wall model: the viscous wall flux is the
+    // modelled shear stress (negative on an upper wall), the own normal
+    // stress and no energy flux
+    bool wm = false;
+    if (VISC && fwall && mesh.tauw != nullptr &&
+        pick3(mesh.bc[0], mesh.bc[1], mesh.bc[2], ft.d) == DG_BC_WALL_MODEL) {
+      wm = true;
+      const long long w = wall_face_index(mesh, fx, fy, fz, ft.d, ft.up);
+      const double* tw = mesh.tauw + w * 3 * NF + ft.ab;
+      const double sg = ft.up ? -1.0 : 1.0;
+      fvn[0] = ft.d == 0 ? fvo[0] : sg * tw[0];
+      fvn[1] = ft.d == 1 ? fvo[1] : sg * tw[NF];
+      fvn[2] = ft.d == 2 ? fvo[2] : sg * tw[2 * NF];
+      fvn[3] = 0.0;
+    }
     double corr[5];
     if constexpr (EC) {
       if (ft.d == 0) surface_correction_ec<0>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
@@ -983,6 +1000,15 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       if (ft.d == 0) surface_correction<0>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
       if (ft.d == 1) surface_correction<1>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
       if (ft.d == 2) surface_correction<2>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    }
+    if (wm) {
+      // the wall branch above subtracted the isothermal wall's viscous flux
+      // (own stresses, heat flux only); swap in the wall-model flux fvn
+      const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+      const double iso_e = fvo[3] - (A[1] * fvo[0] + A[2] * fvo[1] + A[3] * fvo[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) corr[1 + c] += sc * (fvo[c] - fvn[c]);
+      corr[4] += sc * (iso_e - fvn[3]);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) sX[ft.le][ft.f][v][ft.ab] = static_cast<R>(corr[v]);

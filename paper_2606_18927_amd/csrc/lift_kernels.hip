@@ -5,7 +5,8 @@
 // inside the fused right-hand-side kernel instead (fwd_kernels.hip).
 //
 // g_d[i] = s_d ( sum_m D_im q_m + delta_iN (q*_R - q_N)/w_N - delta_i0 (q*_L - q_0)/w_0 ),
-// q* = (q_own + q_nb)/2 on shared faces and (0, 0, 0, T_wall) on walls.
+// q* = (q_own + q_nb)/2 on shared faces; on walls (0, 0, 0, T_wall)
+// (isothermal) or the own values without the normal velocity (wall model).
 #include "dg_device.hpp"
 
 namespace dg {
@@ -45,7 +46,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_lift(const double* __restrict__ 
       load_state(U, stride, te * NN + ft.own_node(), so);
       const Prim Po = primitives(so, ph);
       const double qo[4] = {Po.u, Po.v, Po.w, Po.T};
-      double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};
+      double qs[4];
+      wall_lifting_value(mesh, ft.d, qo, qs);
       if (nb >= 0) {
         double sn[5];
         load_state(U, stride, nb * NN + ft.nb_node(), sn);

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libdgsem.so")
 DG_OK, DG_EINVAL, DG_ESTATE, DG_EHIP, DG_ENONPHYS, DG_EUNSUPPORTED = range(6)
 STATUS_NAMES = {0: "DG_OK", 1: "DG_EINVAL", 2: "DG_ESTATE", 3: "DG_EHIP", 4: "DG_ENONPHYS",
                 5: "DG_EUNSUPPORTED"}
-BC = {"periodic": 0, "wall": 1}
+BC = {"periodic": 0, "wall": 1, "wallmodel": 2}
 PRECISION = {"fp64": 0, "mixed": 1, "mixed_noref": 2}
 FLUX = {"kg_llf": 0, "ec_roe": 1}
 
@@ -37,7 +37,7 @@ class DgsemError(RuntimeError):
 class MeshDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("nelem", ctypes.c_int * 3),
                 ("faces", ctypes.POINTER(ctypes.c_double) * 3), ("bc", ctypes.c_int * 3),
-                ("T_wall", ctypes.c_double)]
+                ("T_wall", ctypes.c_double), ("wm_node", ctypes.c_int)]
 
 
 class Physics(ctypes.Structure):
@@ -135,6 +135,7 @@ class MeshSpec:
     faces: tuple               # three 1-D arrays
     bc: tuple = ("periodic", "periodic", "periodic")
     T_wall: float = 1.0
+    wm_node: int = 1           # interface node of "wallmodel" ends
 
     @property
     def nelem(self):
@@ -159,6 +160,7 @@ class Solver:
             desc.faces[d] = self._faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             desc.bc[d] = BC[mesh.bc[d]]
         desc.T_wall = mesh.T_wall
+        desc.wm_node = mesh.wm_node
         phys = Physics(gamma, R, mu, Pr, 1 if viscous else 0, PRECISION[precision], 1 if central_only else 0,
                        FLUX[flux])
         ctx = _P()

@@ -104,3 +104,94 @@ def test_wall_model_no_walls_and_errors():
     with pytest.raises(dgsem.DgsemError) as ei:
         S.wall_stress(U, 4)
     assert ei.value.status == dgsem.DG_EINVAL
+
+
+# ------------------------------------------- the wall model in the operator
+
+def _wm_solver(mesh, g, **kw):
+    spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall, mesh.wm_node)
+    return dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, **kw)
+
+
+def _rel_l2(got, ref):
+    g = np.asarray(got).reshape(5, -1)
+    r = np.asarray(ref).reshape(5, -1)
+    return np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)
+
+
+@pytest.mark.parametrize("N,n,bc,wm_node", [
+    (3, (2, 3, 2), ("periodic", "wallmodel", "periodic"), 1),
+    (5, (2, 3, 2), ("periodic", "wallmodel", "periodic"), 3),
+    (3, (2, 2, 3), ("periodic", "wall", "wallmodel"), 2),
+    (3, (2, 2, 2), ("wallmodel", "periodic", "wallmodel"), 3),
+])
+def test_wall_model_rhs_against_oracle(N, n, bc, wm_node):
+    from oracle.dgsem import rhs
+    need_gpu()
+    say("wall-model rhs", N, n, bc, wm_node)
+    rng = np.random.default_rng(40 + N + wm_node)
+    faces = [random_faces(n[d], -1.0, 1.0, rng) if bc[d] != "periodic" else random_faces(n[d], 0.0, 2.0, rng)
+             for d in range(3)]
+    mesh = Mesh(N, tuple(faces), bc=bc, T_wall=1.1, wm_node=wm_node)
+    g = Gas(gamma=1.4, R=1.0 / (1.4 * 0.01), mu=1e-3, Pr=0.72)
+    U = random_state(mesh, g.gamma, g.R, rng, vel_amp=1.0, p_mean=1.0 / (1.4 * 0.01), p_amp=0.05).numpy()
+    S = _wm_solver(mesh, g)
+    got = S.eval_rhs(to_dev(U)).cpu().numpy()
+    S.sync()
+    ref = rhs(torch.as_tensor(U), mesh, g).numpy()
+    e = _rel_l2(got, ref)
+    say("  rel L2", e)
+    assert np.all(e < 1e-12)
+
+
+def test_wall_model_paper_channel_rhs_and_steps():
+    """The paper's wall-modelled channel: N = 5, (5, 30, 3) elements, 162000 DOF;
+    right-hand side against the oracle at every node, five RK steps against the
+    oracle, and the exact conservation of mass and total energy over the run."""
+    from oracle.dgsem import rhs, rk_step
+    need_gpu()
+    mesh = Mesh(5, (uniform_faces(5, 0, 2 * np.pi), tanh_faces(30, 2.0), uniform_faces(3, 0, np.pi)),
+                bc=("periodic", "wallmodel", "periodic"), T_wall=1.0, wm_node=2)
+    g = Gas(gamma=1.4, R=1.0 / (1.4 * 0.01), mu=1.0 / 180.0 / 18.0, Pr=0.72)
+    U = _channel_state(mesh, g, np.random.default_rng(7))
+    S = _wm_solver(mesh, g)
+    got = S.eval_rhs(to_dev(U)).cpu().numpy()
+    S.sync()
+    ref = rhs(torch.as_tensor(U), mesh, g).numpy()
+    e = _rel_l2(got, ref)
+    say("paper channel rhs rel L2", e, mesh.n_dof, "DOF")
+    assert np.all(e < 1e-12)
+    dt, nsteps = 2e-5, 5  # acoustic CFL about 0.15 at the smallest LGL spacing
+    S.set_state(to_dev(U))
+    S.rk_step(dt, nsteps)
+    S.sync()
+    Un = S.get_state().cpu().numpy().reshape(U.shape)
+    Uref = rk_step(torch.as_tensor(U), mesh, g, dt, nsteps).numpy()
+    e = _rel_l2(Un, Uref)
+    e2 = _rel_l2(Un - U, Uref - U)
+    say("paper channel 5 steps rel L2", e, "increment", e2)
+    assert np.all(e < 1e-12) and np.all(e2 < 1e-9)
+    wq = mesh.quadrature_weights().numpy()
+    for v in (0, 4):
+        i0, i1 = (wq * U[v]).sum(), (wq * Un[v]).sum()
+        assert abs(i1 - i0) < 1e-13 * (wq * np.abs(U[v])).sum()
+    assert (wq * Un[1]).sum() < (wq * U[1]).sum()  # the walls drag the flow
+
+
+def test_wall_model_unsupported_combinations():
+    need_gpu()
+    mesh = Mesh(3, (uniform_faces(2, 0, 1), uniform_faces(2, -1, 1), uniform_faces(2, 0, 1)),
+                bc=("periodic", "wallmodel", "periodic"), wm_node=1)
+    g = Gas(gamma=1.4, R=1.0, mu=1e-3, Pr=0.72)
+    with pytest.raises(dgsem.DgsemError) as ei:
+        _wm_solver(mesh, g, precision="mixed")
+    assert ei.value.status == dgsem.DG_EUNSUPPORTED
+    S = _wm_solver(mesh, g, with_adjoint=True)
+    U = to_dev(np.ones((5,) + mesh.shape) * np.array([1, 0.1, 0, 0, 3.0])[:, None, None, None, None, None, None])
+    with pytest.raises(dgsem.DgsemError) as ei:
+        S.eval_rhs_vjp(U, U)
+    assert ei.value.status == dgsem.DG_EUNSUPPORTED
+    bad = Mesh(3, mesh.faces, bc=mesh.bc, wm_node=4)
+    with pytest.raises(dgsem.DgsemError) as ei:
+        _wm_solver(bad, g)
+    assert ei.value.status == dgsem.DG_EINVAL
