@@ -145,7 +145,7 @@ def test_wall_model_rhs_against_oracle(N, n, bc, wm_node):
 
 
 def test_wall_model_paper_channel_rhs_and_steps():
-    """The paper's wall-modelled channel: N = 5, (5, 30, 3) elements, 162000 DOF;
+    """The paper's wall-modelled channel: N = 5, (5, 30, 3) elements (97200 DOF);
     right-hand side against the oracle at every node, five RK steps against the
     oracle, and the exact conservation of mass and total energy over the run."""
     from oracle.dgsem import rhs, rk_step
