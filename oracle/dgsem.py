@@ -208,7 +208,7 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
 
         fc = euler_flux(P, d)
         if viscous:
-            fv = viscous_flux(P.vel, grad, d, gas)
+            fv = viscous_flux(P.vel, grad, d, gas, P.T)
             vol_v = [_apply_D(f, D, na) for f in fv]
         else:
             fv = [torch.zeros_like(U[0]) for _ in range(5)]
@@ -237,7 +237,7 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
             # below an upper wall is the negative), the own normal viscous stress,
             # and no energy flux (adiabatic, stationary wall)
             from .wallmodel import wall_stress_field
-            tau = torch.as_tensor(wall_stress_field(U, mesh, gas, mesh.wm_node, lambda T: gas.mu))
+            tau = torch.as_tensor(wall_stress_field(U, mesh, gas, mesh.wm_node, gas.mu_of))
             wall_index = [dd for dd in range(3) if mesh.bc[dd] != "periodic"]
             base = 0
             for dd in wall_index:
@@ -255,7 +255,7 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
                 fwc = wall_convective_flux(plane_P, d)
                 if viscous:
                     g_plane = [[grad[c][b].select(na, idx) for b in range(3)] for c in range(4)]
-                    fvo = viscous_flux(plane_P.vel, g_plane, d, gas)
+                    fvo = viscous_flux(plane_P.vel, g_plane, d, gas, plane_P.T)
                 fwv = [torch.zeros_like(plane_P.p) for _ in range(5)]
                 for c in range(3):
                     if not viscous:
@@ -275,7 +275,7 @@ def rhs(U: torch.Tensor, mesh: Mesh, gas: Gas, *, viscous: bool = True,
                 fwc = wall_convective_flux(plane_P, d)
                 if viscous:
                     zv = zero.select(na, idx)
-                    fwv = viscous_flux((zv, zv, zv), g_plane, d, gas)
+                    fwv = viscous_flux((zv, zv, zv), g_plane, d, gas, plane_P.T)
                 else:
                     fwv = [torch.zeros_like(plane_P.p)] * 5
                 mask = _end_mask(plane_P.p, ea, last)

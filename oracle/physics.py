@@ -1,10 +1,11 @@
 """Gas model and fluxes of the oracle (test infrastructure only).
 
 Paper Sec. 4: the working fluid is an ideal gas and the scheme is a split-form
-DG discretisation with viscous fluxes.  The paper's own production choices
-(Chandrashekar entropy-conserving volume flux, Roe/Harten surface flux,
-Sutherland viscosity) are not the configuration built here; the workloads use
-the readings below, each written from its published definition:
+DG discretisation with viscous fluxes.  The default configuration uses the
+readings below, each written from its published definition; the paper's own
+production choices (Chandrashekar entropy-conserving volume flux, Roe/Harten
+surface flux, Sutherland viscosity) are options described further down and
+in the viscous-flux item:
 
 * ideal gas:   p = (gamma - 1) (E - rho |u|^2 / 2),   T = p / (rho R),
                c = sqrt(gamma p / rho),   e = E / rho;
@@ -14,9 +15,14 @@ the readings below, each written from its published definition:
 * Kennedy-Gruber two-point volume flux, {{x}} = (x_a + x_b) / 2:
                f#_d = ({{rho}}{{u_d}}, {{rho}}{{u_d}}{{u}} + {{p}} delta_1d, ...,
                        {{rho}}{{u_d}}{{e}} + {{p}}{{u_d}});
-* Newtonian/Fourier viscous flux with constant viscosity mu,
+* Newtonian/Fourier viscous flux,
   tau = mu (grad u + grad u^T - 2/3 (div u) I), kappa = mu gamma R / ((gamma-1) Pr):
-               f_v,d = (0, tau_1d, tau_2d, tau_3d, u_a tau_ad + kappa dT/dx_d);
+               f_v,d = (0, tau_1d, tau_2d, tau_3d, u_a tau_ad + kappa dT/dx_d),
+  with mu constant, or (Sec. 4 names Sutherland's law for the working fluid)
+  mu(T) = mu_ref (T / T_ref)^(3/2) (T_ref + S) / (T + S), mu_ref the
+  viscosity at T_ref and S Sutherland's temperature, both in the units of T;
+  mu and kappa are taken at the temperature of the node whose gradients form
+  the flux (at a wall: the interior face node);
 * local Lax-Friedrichs (Rusanov) surface flux whose central part is the
   Kennedy-Gruber flux: F* = f#_d(U_L, U_R) - lambda/2 (U_R - U_L),
   lambda = max(|u_d,L| + c_L, |u_d,R| + c_R);
@@ -73,10 +79,23 @@ class Gas:
     R: float = 1.0
     mu: float = 0.0
     Pr: float = 0.72
+    sutherland: bool = False  # mu(T) by Sutherland's law, mu being its value at T_ref
+    T_ref: float = 1.0
+    S: float = 0.0
 
     @property
     def kappa(self) -> float:
         return self.mu * self.gamma * self.R / ((self.gamma - 1.0) * self.Pr)
+
+    def mu_of(self, T):
+        """Dynamic viscosity at temperature T (a number or a tensor)."""
+        if not self.sutherland:
+            return self.mu
+        return self.mu * (T / self.T_ref) ** 1.5 * (self.T_ref + self.S) / (T + self.S)
+
+    def kappa_of(self, T):
+        """Heat conductivity mu(T) c_p / Pr at temperature T."""
+        return self.mu_of(T) * self.gamma * self.R / ((self.gamma - 1.0) * self.Pr)
 
     @property
     def cv(self) -> float:
@@ -154,9 +173,13 @@ def kg_flux(A: Prim, B: Prim, d: int):
     return f
 
 
-def viscous_flux(vel, grad, d: int, gas: Gas):
-    """f_v,d for velocity vel = (u, v, w) and grad[q][b] = d q / d x_b, q in (u, v, w, T)."""
-    mu = gas.mu
+def viscous_flux(vel, grad, d: int, gas: Gas, T=None):
+    """f_v,d for velocity vel = (u, v, w) and grad[q][b] = d q / d x_b, q in (u, v, w, T);
+    T (needed with Sutherland's law) is the temperature at which mu and kappa are taken."""
+    if gas.sutherland and T is None:
+        raise ValueError("Sutherland's law needs the temperature")
+    mu = gas.mu_of(T)
+    kappa = gas.kappa_of(T)
     div = grad[0][0] + grad[1][1] + grad[2][2]
     tau = []
     for a in range(3):
@@ -164,7 +187,7 @@ def viscous_flux(vel, grad, d: int, gas: Gas):
         if a == d:
             t = t - (2.0 / 3.0) * mu * div
         tau.append(t)
-    energy = vel[0] * tau[0] + vel[1] * tau[1] + vel[2] * tau[2] + gas.kappa * grad[3][d]
+    energy = vel[0] * tau[0] + vel[1] * tau[1] + vel[2] * tau[2] + kappa * grad[3][d]
     zero = torch.zeros_like(tau[0])
     return [zero, tau[0], tau[1], tau[2], energy]
 

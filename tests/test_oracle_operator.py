@@ -275,6 +275,9 @@ def _mms_source(g):
     gam, R, mu, Pr = sp.Float(g.gamma), sp.Float(g.R), sp.Float(g.mu), sp.Float(g.Pr)
     E = p / (gam - 1) + rho * (u ** 2 + v ** 2 + w ** 2) / 2
     T = p / (rho * R)
+    if g.sutherland:  # mu(T) = mu_ref (T / T_ref)^(3/2) (T_ref + S) / (T + S)
+        Tr, Sg = sp.Float(g.T_ref), sp.Float(g.S)
+        mu = mu * (T / Tr) ** sp.Rational(3, 2) * (Tr + Sg) / (T + Sg)
     kap = mu * gam * R / ((gam - 1) * Pr)
     vel = [u, v, w]
     X = [x, y, z]
@@ -323,6 +326,39 @@ def test_manufactured_truncation_error_order_N(N):
     for v in range(5):
         eoc = math.log2(errs[0][v] / errs[1][v])
         assert eoc > N - 0.35, (v, errs, eoc)
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_manufactured_truncation_error_order_N_sutherland(N):
+    """As above with Sutherland's law (T_ref = 0.5, S = 5 T_ref, so mu ~ T^(3/2)
+    over the solution's T = p / rho in 0.43..0.58): the residual converges at
+    rate N, while the constant-viscosity operator's residual against the same
+    source stalls at the model error (N = 4: 20x the Sutherland residual and
+    more), so a viscosity or conductivity left constant anywhere fails."""
+    from oracle.physics import Gas
+    g = Gas(gamma=1.4, R=1.0, mu=0.05, Pr=0.72, sutherland=True, T_ref=0.5, S=2.5)
+    g0 = Gas(gamma=1.4, R=1.0, mu=0.05, Pr=0.72)
+    S, Uf = _mms_source(g)
+    errs, errs0 = [], []
+    for n in (4, 8):
+        m = Mesh(N, (uniform_faces(n, 0, TWO_PI),) * 3)
+        X, Y, Z = m.coords()
+        U0 = torch.stack([_eval(f, X, Y, Z, 0.0) for f in Uf])
+        h = 1e-6
+        dUdt = (torch.stack([_eval(f, X, Y, Z, h) for f in Uf])
+                - torch.stack([_eval(f, X, Y, Z, -h) for f in Uf])) / (2 * h)
+        src = torch.stack([_eval(f, X, Y, Z, 0.0) for f in S])
+        wq = m.quadrature_weights()
+        r = rhs(U0, m, g, source=src) - dUdt
+        r0 = rhs(U0, m, g0, source=src) - dUdt
+        errs.append([math.sqrt((wq * r[v] ** 2).sum().item()) for v in range(5)])
+        errs0.append([math.sqrt((wq * r0[v] ** 2).sum().item()) for v in range(5)])
+    for v in range(5):
+        eoc = math.log2(errs[0][v] / errs[1][v])
+        assert eoc > N - 0.35, (v, errs, eoc)
+    if N == 4:
+        for v in range(1, 5):
+            assert errs0[1][v] > 20 * errs[1][v], (v, errs, errs0)
 
 
 @pytest.mark.slow
