@@ -66,6 +66,15 @@ typedef enum {
                              central part the Chandrashekar flux.  DG_FP64 only; no
                              adjoint (the VJP calls return DG_EUNSUPPORTED)            */
 
+/* Viscosity laws (dg_physics.viscosity). */
+#define DG_VISC_CONSTANT 0    /* mu constant                                              */
+#define DG_VISC_SUTHERLAND 1  /* Sutherland's law, the paper's (Sec. 4) for its working
+                                 fluid: mu(T) = mu (T / T_ref)^(3/2) (T_ref + S) / (T + S),
+                                 mu being the viscosity at T_ref; T_ref and S in the units
+                                 of T; taken at each node's temperature (at a wall: the
+                                 interior face node's; in the wall model: the wall
+                                 temperature's).  DG_FP64 only; no adjoint               */
+
 typedef struct dg_ctx dg_ctx;
 
 /* Mesh description.  faces[d] are host arrays of nelem[d] + 1 strictly
@@ -81,8 +90,9 @@ typedef struct {
                          at DG_BC_WALL_MODEL ends; ignored otherwise            */
 } dg_mesh_desc;
 
-/* Gas and scheme switches.  Viscosity is constant; the heat conductivity is
- * kappa = mu gamma R / ((gamma - 1) Pr).                                     */
+/* Gas and scheme switches.  The heat conductivity is
+ * kappa(T) = mu(T) gamma R / ((gamma - 1) Pr).  The fields after `flux` may be
+ * left zero (constant viscosity).                                            */
 typedef struct {
   double gamma, R, mu, Pr;
   int viscous;        /* 0: Euler fluxes only (no lifting), 1: Navier-Stokes      */
@@ -93,6 +103,9 @@ typedef struct {
   int central_only;   /* 1: drop the surface dissipation (Lax-Friedrichs or Roe):
                          test switch                                             */
   int flux;           /* DG_FLUX_KG_LLF or DG_FLUX_EC_ROE                          */
+  int viscosity;      /* DG_VISC_CONSTANT or DG_VISC_SUTHERLAND                     */
+  double T_ref, S;    /* Sutherland's law: reference temperature (> 0) and
+                         Sutherland's temperature (>= 0); ignored otherwise      */
 } dg_physics;
 
 /* Library version string (static storage). */
@@ -105,8 +118,10 @@ dg_status dg_lgl(int N, double* xi, double* w);
 /* Validate the mesh and physics, build the host tables and create a context
  * on `hip_stream` (a hipStream_t, NULL = default stream).  No device work.
  * Errors: DG_EINVAL (null pointers, non-monotone faces, bad bc, gamma <= 1,
- * R <= 0, mu < 0, Pr <= 0, empty mesh, unknown precision or flux),
- * DG_EUNSUPPORTED (N not in {3, 5, 7}; DG_FLUX_EC_ROE with mixed precision). */
+ * R <= 0, mu < 0, Pr <= 0, empty mesh, unknown precision, flux or viscosity
+ * law, Sutherland's law with T_ref <= 0 or S < 0),
+ * DG_EUNSUPPORTED (N not in {3, 5, 7}; DG_FLUX_EC_ROE, DG_BC_WALL_MODEL or
+ * DG_VISC_SUTHERLAND with mixed precision).                                  */
 dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* hip_stream,
                        dg_ctx** out);
 
@@ -140,7 +155,9 @@ dg_status dg_eval_lift(dg_ctx* ctx, const double* U_dev, double* grad_dev);
 dg_status dg_rk_step(dg_ctx* ctx, double t, double dt, int nsteps);
 
 /* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs.  Needs a
- * workspace bound with_adjoint.  FP64 arithmetic.                            */
+ * workspace bound with_adjoint.  FP64 arithmetic.  The VJP calls cover the
+ * Kennedy-Gruber / Lax-Friedrichs fluxes with constant viscosity and
+ * isothermal or periodic ends; other contexts get DG_EUNSUPPORTED.          */
 dg_status dg_eval_rhs_vjp(dg_ctx* ctx, const double* U_dev, const double* lam_dev,
                           double* Ubar_dev, double t);
 
@@ -180,7 +197,7 @@ dg_status dg_wall_faces(const dg_ctx* ctx, long long* n_faces);
  * velocity u_par (normal component removed) and its direction t; the Van
  * Driest transform for an adiabatic wall, u_VD = a asin(u_par / a),
  * a^2 = 2 c_p T_w / r, T_w = T + r u_par^2 / (2 c_p), r = Pr^(1/3); wall
- * density p / (R T_w) and viscosity mu; u_tau from Spalding's law
+ * density p / (R T_w) and viscosity mu(T_w); u_tau from Spalding's law
  * h u_tau / nu_w = f(u_VD / u_tau), f(u+) = u+ + 0.1108 (exp(0.4 u+) - 1 -
  * 0.4 u+ - (0.4 u+)^2/2 - (0.4 u+)^3/6 - (0.4 u+)^4/24) (Newton, from below).
  * Writes tau_dev[(face 3 + c) (N+1)^2 + a + (N+1) b] = rho_w u_tau^2 t_c for

@@ -106,6 +106,9 @@ dg::DevPhys dev_phys(const dg_ctx* c) {
   p.central = c->phys.central_only;
   p.mixed_ref = c->phys.precision == DG_MIXED ? 1 : 0;
   p.ec = c->phys.flux == DG_FLUX_EC_ROE ? 1 : 0;
+  p.suth = c->phys.viscosity == DG_VISC_SUTHERLAND ? 1 : 0;
+  p.suth_S = p.suth ? c->phys.S : 0.0;
+  p.suth_c = p.suth ? (c->phys.T_ref + c->phys.S) / (c->phys.T_ref * std::sqrt(c->phys.T_ref)) : 1.0;
   return p;
 }
 
@@ -228,6 +231,8 @@ dg_status need_adjoint(dg_ctx* c) {
   if (c->phys.flux != DG_FLUX_KG_LLF)
     return fail(c, DG_EUNSUPPORTED, "the adjoint is built for the Kennedy-Gruber / Lax-Friedrichs fluxes");
   if (c->wall_model) return fail(c, DG_EUNSUPPORTED, "the adjoint does not cover the wall model");
+  if (c->phys.viscosity != DG_VISC_CONSTANT)
+    return fail(c, DG_EUNSUPPORTED, "the adjoint is built for constant viscosity");
   return DG_OK;
 }
 
@@ -272,6 +277,12 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
     return DG_EINVAL;
   if (phys->flux != DG_FLUX_KG_LLF && phys->flux != DG_FLUX_EC_ROE) return DG_EINVAL;
   if (phys->flux == DG_FLUX_EC_ROE && phys->precision != DG_FP64) return DG_EUNSUPPORTED;
+  if (phys->viscosity != DG_VISC_CONSTANT && phys->viscosity != DG_VISC_SUTHERLAND) return DG_EINVAL;
+  if (phys->viscosity == DG_VISC_SUTHERLAND) {
+    if (!(phys->T_ref > 0.0) || !(phys->S >= 0.0) || !std::isfinite(phys->T_ref) || !std::isfinite(phys->S))
+      return DG_EINVAL;
+    if (phys->precision != DG_FP64) return DG_EUNSUPPORTED;
+  }
   const bool wall_model = mesh->bc[0] == DG_BC_WALL_MODEL || mesh->bc[1] == DG_BC_WALL_MODEL ||
                           mesh->bc[2] == DG_BC_WALL_MODEL;
   if (wall_model && (mesh->wm_node < 1 || mesh->wm_node > mesh->N)) return DG_EINVAL;

@@ -169,6 +169,12 @@ __device__ inline Prim primitives(const double s[5], const DevPhys& ph) {
   return P;
 }
 
+// mu(T) / mu (= kappa(T) / kappa): 1 for constant viscosity; Sutherland's law
+// (T / T_ref)^(3/2) (T_ref + S) / (T + S) = c T sqrt(T) / (T + S).
+__device__ inline double viscosity_ratio(const DevPhys& ph, double T) {
+  return ph.suth ? ph.suth_c * T * sqrt(T) / (T + ph.suth_S) : 1.0;
+}
+
 __device__ inline double vel(const Prim& P, int d) { return d == 0 ? P.u : (d == 1 ? P.v : P.w); }
 
 __device__ inline void load_state(const double* U, long long stride, long long idx, double u[5]) {

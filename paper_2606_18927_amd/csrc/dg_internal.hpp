@@ -31,6 +31,8 @@ struct DevPhys {
   int viscous, central;
   int mixed_ref;      // mixed precision: subtract the element reference state
   int ec;             // Chandrashekar volume flux and Roe surface flux
+  int suth;           // Sutherland's law: mu(T) = mu suth_c T^(3/2) / (T + suth_S)
+  double suth_S, suth_c;
 };
 
 // LGL tables of one N, held in device memory inside the workspace.

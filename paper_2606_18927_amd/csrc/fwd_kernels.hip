@@ -307,10 +307,15 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     R g[12];
     lifted_gradients<N, R, V2>(sD, sq[le], ssq[le], i, j, k, static_cast<R>(mesh.s[0][ex]),
                                static_cast<R>(mesh.s[1][ey]), static_cast<R>(mesh.s[2][ez]), g);
-    const R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
     const int l = Gm::lds(i, j, k);
     const V2 uv = sq[le][0][l], wT = sq[le][1][l];
     const R u = uv.x, v = uv.y, w = wT.x;
+    R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
+    if (ph.suth) {  // FP64 contexts only: LDS holds T itself (no reference value)
+      const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(wT.y)));
+      mu *= r;
+      kappa *= r;
+    }
     R* out = ffv + e * (6 * 4 * NF);
     R f[4];
     if (i == 0 || i == N) {
@@ -874,7 +879,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       lifted_gradients_half<N, R, V2, !EC>(sD, sp[le], sT, ssq[le], i, j, k,
                                       static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
                                       static_cast<R>(mesh.s[2][ez]), g);
-      stress<R>(g, mu, kappa, tau, qT);
+      if (ph.suth) {  // FP64 contexts only: sT holds T itself (no reference value)
+        const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(sT[l])));
+        stress<R>(g, mu * r, kappa * r, tau, qT);
+      } else {
+        stress<R>(g, mu, kappa, tau, qT);
+      }
     }
     __syncthreads();
   }

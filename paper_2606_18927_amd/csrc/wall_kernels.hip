@@ -9,7 +9,8 @@
 //   k = kappa u+.  F is increasing and concave in x, so Newton steps from any
 //   point with F <= 0 increase monotonically to the root.
 // Output per wall face: tau[(face * 3 + c) * NF + ab], the wall-stress vector
-// rho_w u_tau^2 t along the wall-parallel velocity direction t.
+// rho_w u_tau^2 t along the wall-parallel velocity direction t.  The wall
+// viscosity is the gas model's at T_w (constant, or Sutherland's law).
 #include "dg_device.hpp"
 
 namespace dg {
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_wall_stress(const double* __restrict__ 
   const double a = sqrt(2.0 * cp * T_w / recovery);
   const double u_vd = a * asin(u_par / a);
   const double rho_w = P.p / (ph.R * T_w);
-  const double nu_w = ph.mu / rho_w;
+  const double nu_w = ph.mu * viscosity_ratio(ph, T_w) / rho_w;
   const double sd = d == 0 ? mesh.s[0][ex] : (d == 1 ? mesh.s[1][ey] : mesh.s[2][ez]);
   const double h = xi_wm1 / sd;  // (xi_nwm + 1) width / 2
   const double u_tau = solve_u_tau(u_vd, h, nu_w);

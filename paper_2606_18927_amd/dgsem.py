@@ -43,7 +43,8 @@ class MeshDesc(ctypes.Structure):
 class Physics(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("R", ctypes.c_double), ("mu", ctypes.c_double),
                 ("Pr", ctypes.c_double), ("viscous", ctypes.c_int), ("precision", ctypes.c_int),
-                ("central_only", ctypes.c_int), ("flux", ctypes.c_int)]
+                ("central_only", ctypes.c_int), ("flux", ctypes.c_int), ("viscosity", ctypes.c_int),
+                ("T_ref", ctypes.c_double), ("S", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -147,7 +148,9 @@ class Solver:
 
     def __init__(self, mesh: MeshSpec, gamma: float, R: float, mu: float, Pr: float, *,
                  viscous: bool = True, precision: str = "fp64", central_only: bool = False,
-                 flux: str = "kg_llf", with_adjoint: bool = False, device=None):
+                 flux: str = "kg_llf", sutherland: tuple | None = None, with_adjoint: bool = False,
+                 device=None):
+        """sutherland = (T_ref, S) selects Sutherland's law, mu being the viscosity at T_ref."""
         L = lib()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
@@ -161,8 +164,9 @@ class Solver:
             desc.bc[d] = BC[mesh.bc[d]]
         desc.T_wall = mesh.T_wall
         desc.wm_node = mesh.wm_node
+        T_ref, S = sutherland if sutherland is not None else (0.0, 0.0)
         phys = Physics(gamma, R, mu, Pr, 1 if viscous else 0, PRECISION[precision], 1 if central_only else 0,
-                       FLUX[flux])
+                       FLUX[flux], 1 if sutherland is not None else 0, T_ref, S)
         ctx = _P()
         st = L.dg_init_mesh(ctypes.byref(desc), ctypes.byref(phys), self.stream.cuda_stream, ctypes.byref(ctx))
         if st != DG_OK:

@@ -70,10 +70,12 @@ def _init(L, desc, phys):
 
 
 def _phys(**kw):
-    base = dict(gamma=1.4, R=1.0, mu=0.01, Pr=0.72, viscous=1, precision=0, central_only=0, flux=0)
+    base = dict(gamma=1.4, R=1.0, mu=0.01, Pr=0.72, viscous=1, precision=0, central_only=0, flux=0,
+                viscosity=0, T_ref=0.0, S=0.0)
     base.update(kw)
     return dgsem.Physics(base["gamma"], base["R"], base["mu"], base["Pr"], base["viscous"],
-                         base["precision"], base["central_only"], base["flux"])
+                         base["precision"], base["central_only"], base["flux"], base["viscosity"],
+                         base["T_ref"], base["S"])
 
 
 def test_init_mesh_validation_errors(L):
@@ -90,6 +92,18 @@ def test_init_mesh_validation_errors(L):
     L.dg_free(ctx)
     assert _init(L, d, _phys(flux=1, precision=1))[0] == dgsem.DG_EUNSUPPORTED
     assert _init(L, d, _phys(flux=2))[0] == dgsem.DG_EINVAL
+    # viscosity law: Sutherland's needs T_ref > 0 and S >= 0, and is FP64 only
+    st, ctx = _init(L, d, _phys(viscosity=1, T_ref=1.0, S=0.38))
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
+    assert _init(L, d, _phys(viscosity=1, T_ref=1.0, S=0.38, precision=1))[0] == dgsem.DG_EUNSUPPORTED
+    for bad in (dict(viscosity=2), dict(viscosity=1, T_ref=0.0, S=0.38), dict(viscosity=1, T_ref=1.0, S=-1.0),
+                dict(viscosity=1, T_ref=float("inf"), S=0.38)):
+        assert _init(L, d, _phys(**bad))[0] == dgsem.DG_EINVAL, bad
+    # a constant-viscosity context ignores T_ref and S
+    st, ctx = _init(L, d, _phys(T_ref=-1.0, S=-1.0))
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
     d, keep = _desc(faces=(np.array([0.0, 0.5, 0.4]), np.linspace(0, 1, 3), np.linspace(0, 1, 3)))
     assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL          # non-monotone faces
     d, keep = _desc(bc=(0, 7, 0))
