@@ -13,6 +13,11 @@ paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
   mixed         the same step in mixed precision (when requested / available);
   ec_roe        the same step with the entropy-conserving volume flux and the
                 Roe surface flux (FP64);
+  sutherland    the same step with Sutherland's viscosity law (FP64);
+  wall_model    the N = 5, 48x32x48 channel with wall-modelled slip walls and
+                Sutherland's law (FP64) beside the same channel with
+                isothermal walls and constant viscosity, and the wall-stress
+                kernel alone (algorithmic bytes over its event-timed launch);
   adjoint       adjoint/forward time ratio (when available).
 """
 
@@ -78,6 +83,8 @@ def _parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ec", action="store_true", help="skip the entropy-conserving / Roe flux leg")
+    ap.add_argument("--no-physics", action="store_true",
+                    help="skip the Sutherland and wall-model legs")
     ap.add_argument("--adjoint-steps", type=int, default=50)
     return ap.parse_args()
 
@@ -99,9 +106,57 @@ def time_steps(S, dt, steps, warmup):
     return ms, lift_ms, rk_ms, n_lift, n_rk
 
 
+def _leg(wl_name, r):
+    return {"workload": wl_name, "ns_per_dof_stage": r["ns_per_dof_stage"], "ms_per_step": r["ms_per_step"],
+            "rk_kernel_ms": r["rk_kernel_ms"], "face_kernel_ms": r["face_kernel_ms"],
+            "step_alg_gbs": r["step_alg_gbs"], "step_frac": r["step_alg_gbs"] / HBM_PEAK_GBS}
+
+
+def run_wall_model(steps, warmup):
+    """The wall-modelled channel (FP64, Sutherland) beside the isothermal one,
+    and the wall-stress kernel alone: per wall-face node it reads the
+    interface node's state (40 B) and writes the stress vector (24 B)."""
+    import torch
+
+    from paper_2606_18927_amd import dgsem, workloads
+    wl = workloads.WORKLOADS["channel_n5_48x32x48_wm"]
+    wl_iso = workloads.WORKLOADS["channel_n5_48x32x48"]
+    xi, _ = dgsem.lgl(wl.N)
+    U, dt = workloads.make_state(wl, xi)
+    out = {}
+    r, Ud = run_precision(wl, U, dt, "fp64", steps, warmup)
+    out["wall_model"] = _leg(wl.name, r)
+    r, _ = run_precision(wl_iso, U, dt, "fp64", steps, warmup)
+    out["isothermal_constant_mu"] = _leg(wl_iso.name + " (fp64)", r)
+    S = dgsem.solver_for(wl, precision="fp64")
+    NP = wl.N + 1
+    nodes = S.wall_faces() * NP * NP
+    tau = torch.empty(nodes * 3, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        S.wall_stress(Ud, wl.wm_node, tau)
+    S.sync()
+    reps = 50
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(S.stream)
+    for _ in range(reps):
+        S.wall_stress(Ud, wl.wm_node, tau)
+    e1.record(S.stream)
+    torch.cuda.synchronize()
+    S.sync()
+    ms = e0.elapsed_time(e1) / reps
+    alg = nodes * (40 + 24)
+    out["k_wall_stress"] = {"ms_per_launch": ms, "wall_face_nodes": nodes, "alg_bytes": alg,
+                            "gbs": alg / (ms / 1e3) / 1e9, "frac": alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                            "note": "launch- and latency-bound (one Newton solve per lane)"}
+    out["dt"] = dt
+    del S
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl):
-    """The oracle (unchanged) on a periodic 16x16x8-element sample of the same
-    N = 7 Taylor-Green state, three RK steps, on the host's cores."""
+    """The oracle (unchanged) on a periodic 16x16x16-element sample of the same
+    N = 7 Taylor-Green state, four RK steps, on the host's cores."""
     import numpy as np
     import torch
 
@@ -110,7 +165,7 @@ def cpu_baseline(wl):
     from oracle.physics import Gas
     from paper_2606_18927_amd import workloads
 
-    sub = workloads.Workload("tgv_n7_sample", "tgv", wl.N, (16, 16, 8), nsteps=3, noise=wl.noise,
+    sub = workloads.Workload("tgv_n7_sample", "tgv", wl.N, (16, 16, 16), nsteps=4, noise=wl.noise,
                              seed=wl.seed)
     from oracle.basis import lgl
     xi, _ = lgl(sub.N)
@@ -123,7 +178,7 @@ def cpu_baseline(wl):
     sec = time.perf_counter() - t0
     ns = sec * 1e9 / (mesh.n_dof * sub.nsteps * 5)
     return {"value": ns, "unit": "ns/DOF/stage", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"N=7 Taylor-Green, 16x16x8 periodic elements ({mesh.n_dof} DOF), "
+            "sample": f"N=7 Taylor-Green, 16x16x16 periodic elements ({mesh.n_dof} DOF), "
                       f"{sub.nsteps} RK steps, {sec:.1f} s wall, float64 torch CPU",
             "host_cpu_count": os.cpu_count()}
 
@@ -286,6 +341,24 @@ def main():
               "face_kernel_ms": r["face_kernel_ms"], "step_alg_gbs": r["step_alg_gbs"],
               "step_frac": r["step_alg_gbs"] / HBM_PEAK_GBS}
         print(f"[bench] ec_roe {ec['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
+    suth = wall = None
+    if not args.no_physics and wl.name == "tgv_n7_32x32x32":
+        wl_s = workloads.WORKLOADS["tgv_n7_32x32x32_sutherland"]
+        try:
+            r, _ = run_precision(wl_s, U, dt, "fp64", args.steps, args.warmup)
+            suth = _leg(wl_s.name, r)
+            print(f"[bench] sutherland {suth['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
+                  flush=True)
+        except dgsem.DgsemError as e:
+            suth = {"error": str(e)}
+        try:
+            wall = run_wall_model(args.steps, args.warmup)
+            print(f"[bench] wall model channel {wall['wall_model']['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage "
+                  f"(isothermal {wall['isothermal_constant_mu']['ns_per_dof_stage']*1e3:.1f}); "
+                  f"k_wall_stress {wall['k_wall_stress']['ms_per_launch']*1e3:.1f} us", file=sys.stderr,
+                  flush=True)
+        except dgsem.DgsemError as e:
+            wall = {"error": str(e)}
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint(args.adjoint_steps, 25)
@@ -337,6 +410,8 @@ def main():
         "cpu_baseline": cpu,
         "mixed": mixed,
         "ec_roe": ec,
+        "sutherland": suth,
+        "wall_model": wall,
         "adjoint": adjoint,
         "context_mi300a_pid_ns": {"range": [2.457, 4.260], "note": "paper Table 1, 32 APUs, N=7 free stream"},
     }

@@ -19,39 +19,50 @@ namespace {
 constexpr double kKappa = 0.4;
 constexpr double kSpaldingC = 0.1108;
 
-// exp(k) - sum_{n<m} k^n / n! for k >= 0: the series sum_{n>=m} k^n/n! for
-// k <= 5 (no cancellation near 0), the difference above.
-__device__ inline double exp_tail(double k, int m) {
-  if (k > 5.0) {
-    double s = 0.0, t = 1.0;
-    for (int n = 0; n < m; ++n) {
-      s += t;
-      t *= k / (n + 1);
-    }
-    return exp(k) - s;
-  }
-  double t = 1.0;
-  for (int n = 1; n <= m; ++n) t *= k / n;  // k^m / m!
-  double s = 0.0;
-  for (int n = m; n < m + 45; ++n) {
+// f(u+) and f'(u+) of Spalding's law, k = kappa u+:
+//   f = u+ + C T5(k),  f' = 1 + C kappa T4(k),  Tm(k) = exp(k) - sum_{n<m} k^n/n!
+// T5 for k <= 5 as the series sum_{n>=5} k^n/n! (no cancellation near 0; the
+// 40 terms n = 5..44 reach below 1e-25 of the sum), multiplying by the
+// reciprocals 1/n instead of dividing; T4 = T5 + k^4/24.  Above 5 from exp(k).
+template <int n>
+__device__ inline void tail_terms(double k, double& t, double& s) {
+  if constexpr (n < 45) {
     s += t;
-    t *= k / (n + 1);
+    t *= k * (1.0 / (n + 1));
+    tail_terms<n + 1>(k, t, s);
   }
-  return s;
+}
+
+__device__ inline void spalding_f(double up, double& f, double& df) {
+  const double k = kKappa * up;
+  const double k2 = k * k, k4 = k2 * k2;
+  double t5, t4;
+  if (k > 5.0) {
+    const double e = exp(k);
+    const double p3 = 1.0 + k * (1.0 + k * (0.5 + k * (1.0 / 6.0)));
+    t4 = e - p3;
+    t5 = t4 - k4 * (1.0 / 24.0);
+  } else {
+    double t = k4 * k * (1.0 / 120.0), s = 0.0;
+    tail_terms<5>(k, t, s);
+    t5 = s;
+    t4 = s + k4 * (1.0 / 24.0);
+  }
+  f = up + kSpaldingC * t5;
+  df = 1.0 + kSpaldingC * kKappa * t4;
 }
 
 // F(x) and F'(x); F = -inf where exp(kappa u+) would overflow (far below the root)
 __device__ inline void spalding_residual(double x, double u, double h, double nu, double& F,
                                          double& dF) {
   const double up = u / x;
-  const double k = kKappa * up;
-  if (k > 700.0) {
+  if (kKappa * up > 700.0) {
     F = -INFINITY;
     dF = 0.0;
     return;
   }
-  const double f = up + kSpaldingC * exp_tail(k, 5);
-  const double df = 1.0 + kSpaldingC * kKappa * exp_tail(k, 4);  // f'(u+)
+  double f, df;
+  spalding_f(up, f, df);
   F = h * x / nu - f;
   dF = h / nu + df * up / x;
 }

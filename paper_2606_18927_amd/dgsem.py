@@ -314,7 +314,8 @@ class Solver:
 def solver_for(workload, *, device=None, with_adjoint=False, precision=None, viscous=True,
                central_only=False, flux=None) -> Solver:
     """Solver for a paper_2606_18927_amd.workloads.Workload."""
-    mesh = MeshSpec(workload.N, workload.faces(), workload.bc, workload.T_wall)
+    mesh = MeshSpec(workload.N, workload.faces(), workload.bc, workload.T_wall, workload.wm_node)
     return Solver(mesh, workload.gamma, workload.R, workload.mu, workload.Pr, viscous=viscous,
                   precision=precision or workload.precision, central_only=central_only,
-                  flux=flux or workload.flux, with_adjoint=with_adjoint, device=device)
+                  flux=flux or workload.flux, sutherland=workload.sutherland,
+                  with_adjoint=with_adjoint, device=device)

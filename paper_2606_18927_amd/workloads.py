@@ -59,6 +59,9 @@ class Workload:
     cfl: float = 0.5
     checkpoint_every: int = 0
     flux: str = "kg_llf"      # "kg_llf" | "ec_roe"
+    wall: str = "wall"        # channel ends: "wall" (isothermal) | "wallmodel" (slip, modelled stress)
+    wm_node: int = 1          # interface LGL node of "wallmodel" ends
+    sutherland: tuple | None = None  # (T_ref, S) of Sutherland's law; None: constant viscosity
     extra: dict = field(default_factory=dict)
 
     # gas / physics parameters -------------------------------------------
@@ -88,7 +91,7 @@ class Workload:
 
     @property
     def bc(self):
-        return ("periodic", "wall", "periodic") if self.kind == "channel" else ("periodic",) * 3
+        return ("periodic", self.wall, "periodic") if self.kind == "channel" else ("periodic",) * 3
 
     def faces(self):
         nx, ny, nz = self.nelem
@@ -113,6 +116,10 @@ WORKLOADS = {
     # the same with the entropy-conserving volume flux and the Roe surface flux
     "tgv_n7_32x32x32_ec": Workload("tgv_n7_32x32x32_ec", "tgv", 7, (32, 32, 32), nsteps=100,
                                    noise=0.01, seed=TGV_SEED, flux="ec_roe"),
+    # the same with Sutherland's law (air's S / T_ref = 110.4 K / 288.15 K, T_ref = T0)
+    "tgv_n7_32x32x32_sutherland": Workload("tgv_n7_32x32x32_sutherland", "tgv", 7, (32, 32, 32),
+                                           nsteps=100, noise=0.01, seed=TGV_SEED,
+                                           sutherland=(1.0, 110.4 / 288.15)),
     # stretched channel for the adjoint: N=5, 16^3 elements, 50 steps
     "channel_n5_16x16x16": Workload("channel_n5_16x16x16", "channel", 5, (16, 16, 16),
                                     nsteps=50, seed=CHANNEL_SEED),
@@ -120,6 +127,11 @@ WORKLOADS = {
     "channel_n5_48x32x48": Workload("channel_n5_48x32x48", "channel", 5, (48, 32, 48),
                                     nsteps=500, seed=CHANNEL_SEED, precision="mixed",
                                     checkpoint_every=25),
+    # the large channel with wall-modelled slip walls (interface node 2) and
+    # Sutherland's law, FP64
+    "channel_n5_48x32x48_wm": Workload("channel_n5_48x32x48_wm", "channel", 5, (48, 32, 48),
+                                       nsteps=100, seed=CHANNEL_SEED, wall="wallmodel", wm_node=2,
+                                       sutherland=(1.0, 110.4 / 288.15)),
 }
 
 

@@ -26,11 +26,14 @@ def say(*a):
 
 
 def oracle_mesh(wl):
-    return Mesh(wl.N, wl.faces(), bc=wl.bc, T_wall=wl.T_wall)
+    return Mesh(wl.N, wl.faces(), bc=wl.bc, T_wall=wl.T_wall, wm_node=wl.wm_node)
 
 
 def oracle_gas(wl):
-    return Gas(gamma=wl.gamma, R=wl.R, mu=wl.mu, Pr=wl.Pr)
+    if wl.sutherland is None:
+        return Gas(gamma=wl.gamma, R=wl.R, mu=wl.mu, Pr=wl.Pr)
+    return Gas(gamma=wl.gamma, R=wl.R, mu=wl.mu, Pr=wl.Pr, sutherland=True, T_ref=wl.sutherland[0],
+               S=wl.sutherland[1])
 
 
 def state(wl):
