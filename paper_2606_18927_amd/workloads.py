@@ -39,7 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "tgv_faces", "channel_faces", "node_coords",
+__all__ = ["Workload", "WORKLOADS", "tgv_faces", "channel_faces", "node_coords", "warped_nodes",
            "make_state", "cfl_dt", "fd_direction"]
 
 TGV_SEED = 20260001
@@ -162,6 +162,32 @@ def node_coords(xi, faces):
     shape = (nz, ny, nx, NP, NP, NP)
     return (np.broadcast_to(X, shape).copy(), np.broadcast_to(Y, shape).copy(),
             np.broadcast_to(Z, shape).copy())
+
+
+def warped_nodes(xi, nelem, lengths=(2.0 * np.pi,) * 3, amp=0.05):
+    """Node coordinates (3, nz, ny, nx, NP, NP, NP) of a periodic warped box: the
+    uniform tensor mesh of [0, L_x] x [0, L_y] x [0, L_z] with nelem elements,
+    node positions x_lo (1 - xi)/2 + x_hi (1 + xi)/2 (exact at the element
+    ends, so neighbours share their face nodes), each displaced by
+      dx = amp L_x sin(2 pi y / L_y) sin(2 pi z / L_z),
+      dy = amp L_y sin(2 pi x / L_x) sin(2 pi z / L_z),
+      dz = amp L_z sin(2 pi x / L_x) sin(2 pi y / L_y)
+    evaluated at the undisplaced position; the displacement is periodic, so
+    the mesh stays periodic with the box's periods."""
+    xi = np.asarray(xi, dtype=np.float64)
+    NP = xi.size
+    tabs = []
+    for n, L in zip(nelem, lengths):
+        f = L * np.arange(n + 1, dtype=np.float64) / n
+        tabs.append(f[:-1, None] * (1.0 - xi[None, :]) / 2.0 + f[1:, None] * (1.0 + xi[None, :]) / 2.0)
+    nx, ny, nz = nelem
+    shape = (nz, ny, nx, NP, NP, NP)
+    X = np.broadcast_to(tabs[0].reshape(1, 1, nx, 1, 1, NP), shape)
+    Y = np.broadcast_to(tabs[1].reshape(1, ny, 1, 1, NP, 1), shape)
+    Z = np.broadcast_to(tabs[2].reshape(nz, 1, 1, NP, 1, 1), shape)
+    Lx, Ly, Lz = lengths
+    sx, sy, sz = np.sin(2 * np.pi * X / Lx), np.sin(2 * np.pi * Y / Ly), np.sin(2 * np.pi * Z / Lz)
+    return np.stack([X + amp * Lx * sy * sz, Y + amp * Ly * sx * sz, Z + amp * Lz * sx * sy])
 
 
 def _widths(faces):
