@@ -88,6 +88,19 @@ typedef struct {
   double T_wall;      /* wall temperature of DG_BC_ISOTHERMAL_WALL ends          */
   int wm_node;        /* interface LGL node (1..N, from the wall) of the wall model
                          at DG_BC_WALL_MODEL ends; ignored otherwise            */
+  const double* nodes;/* NULL: the axis-aligned elements of `faces`.  Otherwise
+                         curved hexahedra (the paper's production meshes, Sec. 4):
+                         host array of the physical node coordinates
+                         nodes[(n nE + e) (N+1)^3 + node], n = x, y, z, e and node
+                         in the state's canonical order, copied by dg_init_mesh;
+                         each element is the degree-N interpolant of its nodes
+                         (Kopriva's curl-form metric terms, contravariant
+                         two-point fluxes with averaged metrics); the elements
+                         keep the structured connectivity of nelem, all ends
+                         periodic; faces may be NULL.  DG_FP64, DG_FLUX_KG_LLF
+                         only; no adjoint, lifting or kinetic-energy calls
+                         (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
+                         makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;
 
 /* Gas and scheme switches.  The heat conductivity is

@@ -14,7 +14,10 @@ definitions, in the notation of the Cartesian operator (``dgsem``):
   elements of a face the same normal):
       J a^i_n = -1/2 [ curl_xi ( X_l grad_xi X_m - X_m grad_xi X_l ) ]_i,
       (n, m, l) cyclic over (x, y, z), every xi-derivative the collocation
-      derivative D of the nodal product;
+      derivative D of the nodal product; the form is invariant under a
+      translation of X, and it is evaluated (reading) with each element's
+      coordinates taken relative to its first node, so that its rounding is
+      that of the element's size rather than of the coordinates' magnitude;
   J = det(dX_n / dxi^j) with dX/dxi from D (reading);
 * lifting (BR1, strong form; reading: chain rule with the node's own metric):
       J grad q = sum_i J a^i ( sum_m D_im q_m + delta_iN (q*_R - q_N) / w_N
@@ -29,8 +32,12 @@ definitions, in the notation of the Cartesian operator (``dgsem``):
       F#^i(A, B) = sum_d f#_d(A, B) (J a^i_d(A) + J a^i_d(B)) / 2;
     - contravariant physical fluxes F^i = sum_d f_d J a^i_d and
       Fv^i = sum_d f_v,d J a^i_d at each node (own metrics);
-    - the surface flux across a xi^i face with the face node's normal vector
-      s = J a^i (pointing towards +xi^i): local Lax-Friedrichs
+    - the surface flux across a xi^i face, computed once per face with the
+      normal vector s = J a^i of the element below the face at the face node
+      (pointing towards +xi^i; reading: one normal per face, so the flux
+      leaving one element enters the other exactly even where the two
+      elements' face nodes differ in rounding, as at a periodic seam): local
+      Lax-Friedrichs
       F* = sum_d f#_d(L, R) s_d - lambda/2 |s| (U_R - U_L),
       lambda = max(|u_L . n| + c_L, |u_R . n| + c_R), n = s / |s|;
       BR1 central viscous flux Fv* = (Fv^i(L) + Fv^i(R)) / 2.
@@ -98,7 +105,7 @@ def metrics(mesh: CurvMesh):
     """(Ja, J): Ja[i][n] = J a^i_n (i: reference direction, n: physical
     component), each a nodal field; J the Jacobian determinant."""
     D = diff_matrix(mesh.N)
-    X = mesh.X
+    X = mesh.X - mesh.X[..., :1, :1, :1]  # relative to each element's node (0, 0, 0)
     dX = [[_apply_D(X[n], D, NODE_AXIS[j]) for j in range(3)] for n in range(3)]  # dX[n][j] = dX_n/dxi^j
     J = (dX[0][0] * (dX[1][1] * dX[2][2] - dX[1][2] * dX[2][1])
          - dX[0][1] * (dX[1][0] * dX[2][2] - dX[1][2] * dX[2][0])

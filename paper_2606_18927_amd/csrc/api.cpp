@@ -41,7 +41,7 @@ dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 struct Layout {
-  size_t D, w, s[3], status, partial, U0, U1, G, ffv, tauw;
+  size_t D, w, s[3], status, partial, U0, U1, G, ffv, tauw, geo;
   size_t stages, lamG, lamU, ubar, gbar, tmp;
   size_t fwd_end, adj_end;
 };
@@ -69,6 +69,7 @@ Layout layout(const dg_ctx* c) {
   L.G = take(state);
   L.ffv = c->phys.viscous ? take(fbytes) : off;
   L.tauw = c->wall_model ? take(static_cast<size_t>(c->n_wall_faces) * 3 * NP * NP * sizeof(double)) : off;
+  L.geo = c->curvilinear ? take(10 * dof * sizeof(double)) : off;
   L.fwd_end = off;
   L.stages = take(5 * state);
   L.lamG = take(state);
@@ -90,6 +91,7 @@ dg::DevMesh dev_mesh(const dg_ctx* c) {
   m.T_wall = c->T_wall;
   m.nE = c->nE;
   m.tauw = c->wall_model ? c->tauw : nullptr;
+  m.geo = c->curvilinear ? c->geo : nullptr;
   return m;
 }
 
@@ -149,21 +151,41 @@ dg_status wall_model_stress(dg_ctx* c, const double* U) {
                    "wall stress kernel");
 }
 
+// Kernels of one stage for the context's element kind.
+hipError_t face_flux_any(const dg_ctx* c, const dg::DevMesh& m, const dg::DevPhys& p, const dg::DevBasis& b,
+                         const double* U) {
+  if (c->curvilinear) return dg::launch_face_flux_curv(c->N, m, p, b, U, static_cast<double*>(c->ffv), c->stream);
+  return dg::launch_face_flux(c->N, c->phys.precision, m, p, b, U, c->ffv, c->stream);
+}
+
+hipError_t rhs_any(const dg_ctx* c, const dg::DevMesh& m, const dg::DevPhys& p, const dg::DevBasis& b,
+                   const double* U, double* Ut) {
+  if (c->curvilinear)
+    return dg::launch_rhs_curv(c->N, m, p, b, U, static_cast<const double*>(c->ffv), Ut, c->dstatus, c->stream);
+  return dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->ffv, Ut, c->dstatus, c->stream);
+}
+
+hipError_t rk_stage_any(const dg_ctx* c, const dg::DevMesh& m, const dg::DevPhys& p, const dg::DevBasis& b,
+                        const double* U, double* U_out, const dg::Stage& st) {
+  if (c->curvilinear)
+    return dg::launch_rk_stage_curv(c->N, m, p, b, U, static_cast<const double*>(c->ffv), c->G, U_out, st,
+                                    c->dstatus, c->stream);
+  return dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, U, c->ffv, c->G, U_out, st, c->dstatus,
+                             c->stream);
+}
+
 // Lifting (if viscous) then the right-hand side of U into Ut.
 dg_status eval_rhs_into(dg_ctx* c, const double* U, double* Ut) {
   const dg::DevMesh m = dev_mesh(c);
   const dg::DevPhys p = dev_phys(c);
   const dg::DevBasis b = dev_basis(c);
   if (c->phys.viscous) {
-    dg_status st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, U, c->ffv, c->stream),
-                             "face flux kernel");
+    dg_status st = hip_check(c, face_flux_any(c, m, p, b, U), "face flux kernel");
     if (st != DG_OK) return st;
     mark(c, 0);
   }
   if (dg_status st = wall_model_stress(c, U); st != DG_OK) return st;
-  dg_status st = hip_check(c, dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->ffv, Ut, c->dstatus,
-                                             c->stream),
-                           "rhs kernel");
+  dg_status st = hip_check(c, rhs_any(c, m, p, b, U, Ut), "rhs kernel");
   if (st == DG_OK) mark(c, 1);
   return st;
 }
@@ -179,15 +201,12 @@ dg_status forward_stages(dg_ctx* c, const double* in, double dt, Out stage_out) 
   const double* cur = in;
   for (int s = 0; s < 5; ++s) {
     if (c->phys.viscous &&
-        (st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, cur, c->ffv, c->stream),
-                        "face flux kernel")) != DG_OK)
+        (st = hip_check(c, face_flux_any(c, m, p, b, cur), "face flux kernel")) != DG_OK)
       return st;
     if ((st = wall_model_stress(c, cur)) != DG_OK) return st;
     const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
     double* out = stage_out(s);
-    if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, cur, c->ffv, c->G, out,
-                                               stage, c->dstatus, c->stream),
-                        "rk stage kernel")) != DG_OK)
+    if ((st = hip_check(c, rk_stage_any(c, m, p, b, cur, out, stage), "rk stage kernel")) != DG_OK)
       return st;
     cur = out;
   }
@@ -231,6 +250,7 @@ dg_status need_adjoint(dg_ctx* c) {
   if (c->phys.flux != DG_FLUX_KG_LLF)
     return fail(c, DG_EUNSUPPORTED, "the adjoint is built for the Kennedy-Gruber / Lax-Friedrichs fluxes");
   if (c->wall_model) return fail(c, DG_EUNSUPPORTED, "the adjoint does not cover the wall model");
+  if (c->curvilinear) return fail(c, DG_EUNSUPPORTED, "the adjoint is built for axis-aligned elements");
   if (c->phys.viscosity != DG_VISC_CONSTANT)
     return fail(c, DG_EUNSUPPORTED, "the adjoint is built for constant viscosity");
   return DG_OK;
@@ -256,15 +276,18 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   if (!mesh || !phys || !out) return DG_EINVAL;
   *out = nullptr;
   if (mesh->N != 3 && mesh->N != 5 && mesh->N != 7) return DG_EUNSUPPORTED;
+  const bool curved = mesh->nodes != nullptr;
   long long nE = 1;
   for (int d = 0; d < 3; ++d) {
-    if (mesh->nelem[d] <= 0 || !mesh->faces[d]) return DG_EINVAL;
+    if (mesh->nelem[d] <= 0 || (!curved && !mesh->faces[d])) return DG_EINVAL;
     if (mesh->bc[d] != DG_BC_PERIODIC && mesh->bc[d] != DG_BC_ISOTHERMAL_WALL &&
         mesh->bc[d] != DG_BC_WALL_MODEL)
       return DG_EINVAL;
-    for (int i = 0; i < mesh->nelem[d]; ++i) {
-      const double a = mesh->faces[d][i], b = mesh->faces[d][i + 1];
-      if (!(b > a) || !std::isfinite(a) || !std::isfinite(b)) return DG_EINVAL;
+    if (mesh->faces[d]) {
+      for (int i = 0; i < mesh->nelem[d]; ++i) {
+        const double a = mesh->faces[d][i], b = mesh->faces[d][i + 1];
+        if (!(b > a) || !std::isfinite(a) || !std::isfinite(b)) return DG_EINVAL;
+      }
     }
     nE *= mesh->nelem[d];
   }
@@ -291,13 +314,26 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
       mesh->bc[2] == DG_BC_ISOTHERMAL_WALL) {
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;
   }
+  if (curved) {
+    if (mesh->bc[0] != DG_BC_PERIODIC || mesh->bc[1] != DG_BC_PERIODIC || mesh->bc[2] != DG_BC_PERIODIC ||
+        phys->precision != DG_FP64 || phys->flux != DG_FLUX_KG_LLF)
+      return DG_EUNSUPPORTED;
+    const long long n3 = 3 * nE * nn;
+    for (long long q = 0; q < n3; ++q)
+      if (!std::isfinite(mesh->nodes[q])) return DG_EINVAL;
+  }
 
   dg_ctx* c = new (std::nothrow) dg_ctx();
   if (!c) return DG_EINVAL;
   c->N = mesh->N;
   for (int d = 0; d < 3; ++d) {
     c->nelem[d] = mesh->nelem[d];
-    c->faces[d].assign(mesh->faces[d], mesh->faces[d] + mesh->nelem[d] + 1);
+    if (mesh->faces[d]) {
+      c->faces[d].assign(mesh->faces[d], mesh->faces[d] + mesh->nelem[d] + 1);
+    } else {  // curved mesh without faces: unit-width placeholders (the scales are unused)
+      c->faces[d].resize(mesh->nelem[d] + 1);
+      for (int i = 0; i <= mesh->nelem[d]; ++i) c->faces[d][i] = i;
+    }
     c->bc[d] = mesh->bc[d];
     c->s[d].resize(mesh->nelem[d]);
     for (int i = 0; i < mesh->nelem[d]; ++i)
@@ -306,6 +342,8 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   c->T_wall = mesh->T_wall;
   c->wall_model = wall_model;
   c->wm_node = mesh->wm_node;
+  c->curvilinear = curved;
+  if (curved) c->nodes.assign(mesh->nodes, mesh->nodes + 3 * nE * nn);
   c->phys = *phys;
   c->phys.viscous = phys->viscous ? 1 : 0;
   c->phys.central_only = phys->central_only ? 1 : 0;
@@ -355,6 +393,7 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
   c->G = reinterpret_cast<double*>(ws + L.G);
   c->ffv = c->phys.viscous ? static_cast<void*>(ws + L.ffv) : nullptr;
   c->tauw = c->wall_model ? reinterpret_cast<double*>(ws + L.tauw) : nullptr;
+  c->geo = c->curvilinear ? reinterpret_cast<double*>(ws + L.geo) : nullptr;
   if (with_adjoint) {
     c->stages = reinterpret_cast<double*>(ws + L.stages);
     c->lamG = reinterpret_cast<double*>(ws + L.lamG);
@@ -383,6 +422,24 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
   if ((st = hip_check(c, hipMemsetAsync(c->G, 0, 5 * c->n_dof * sizeof(double), c->stream),
                       "clear G")) != DG_OK)
     return st;
+  if (c->curvilinear) {
+    // metric terms from the node coordinates, staged through G (5 values per DOF)
+    const size_t xbytes = 3 * static_cast<size_t>(c->n_dof) * sizeof(double);
+    if ((st = hip_check(c, hipMemcpyAsync(c->G, c->nodes.data(), xbytes, hipMemcpyHostToDevice, c->stream),
+                        "upload nodes")) != DG_OK)
+      return st;
+    if ((st = hip_check(c, dg::launch_metrics(c->N, c->G, c->geo, dev_basis(c), c->nE, c->dstatus, c->stream),
+                        "metrics kernel")) != DG_OK)
+      return st;
+    int bad = 0;
+    if ((st = hip_check(c, hipMemcpyAsync(&bad, c->dstatus, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                        "metrics status")) != DG_OK)
+      return st;
+    if ((st = hip_check(c, hipStreamSynchronize(c->stream), "metrics sync")) != DG_OK) return st;
+    if (bad) return fail(c, DG_EINVAL, "non-positive Jacobian at some node of the curved mesh");
+    if ((st = hip_check(c, hipMemsetAsync(c->G, 0, 5 * c->n_dof * sizeof(double), c->stream), "clear G")) != DG_OK)
+      return st;
+  }
   // the host tables above live in the context, so the asynchronous copies may
   // still be in flight after return; they complete before any later kernel.
   c->bound = true;
@@ -423,6 +480,7 @@ dg_status dg_eval_lift(dg_ctx* c, const double* U, double* grad) {
   if (st != DG_OK) return st;
   if (!U || !grad) return fail(c, DG_EINVAL, "bad pointers");
   if (c->phys.precision != DG_FP64) return fail(c, DG_EUNSUPPORTED, "eval_lift: FP64 contexts only");
+  if (c->curvilinear) return fail(c, DG_EUNSUPPORTED, "eval_lift: axis-aligned elements only");
   return hip_check(c, dg::launch_lift(c->N, dev_mesh(c), dev_phys(c), dev_basis(c), U, grad, c->stream),
                    "lift kernel");
 }
@@ -439,16 +497,13 @@ dg_status dg_rk_step(dg_ctx* c, double /*t*/, double dt, int nsteps) {
       const double* Uin = c->U[c->cur];
       double* Uout = c->U[c->cur ^ 1];
       if (c->phys.viscous) {
-        if ((st = hip_check(c, dg::launch_face_flux(c->N, c->phys.precision, m, p, b, Uin, c->ffv, c->stream),
-                            "face flux kernel")) != DG_OK)
+        if ((st = hip_check(c, face_flux_any(c, m, p, b, Uin), "face flux kernel")) != DG_OK)
           return st;
         mark(c, 0);
       }
       if ((st = wall_model_stress(c, Uin)) != DG_OK) return st;
       const dg::Stage stage{kRkA[s], kRkB[s], dt, s == 0 ? 0 : 1};
-      if ((st = hip_check(c, dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, Uin, c->ffv, c->G,
-                                                 Uout, stage, c->dstatus, c->stream),
-                          "rk stage kernel")) != DG_OK)
+      if ((st = hip_check(c, rk_stage_any(c, m, p, b, Uin, Uout, stage), "rk stage kernel")) != DG_OK)
         return st;
       mark(c, 1);
       c->cur ^= 1;
@@ -543,6 +598,7 @@ dg_status dg_kinetic_energy(dg_ctx* c, const double* U, double* J) {
   dg_status st = need_bound(c);
   if (st != DG_OK) return st;
   if (!U || !J) return fail(c, DG_EINVAL, "bad pointers");
+  if (c->curvilinear) return fail(c, DG_EUNSUPPORTED, "kinetic energy: axis-aligned elements only");
   return hip_check(c, dg::launch_kinetic_energy(c->N, dev_mesh(c), c->dw, U, c->dpartial, c->n_partial,
                                                 inv_volume(c), J, c->stream),
                    "kinetic energy kernels");
@@ -552,6 +608,7 @@ dg_status dg_kinetic_energy_grad(dg_ctx* c, const double* U, double* lam) {
   dg_status st = need_bound(c);
   if (st != DG_OK) return st;
   if (!U || !lam) return fail(c, DG_EINVAL, "bad pointers");
+  if (c->curvilinear) return fail(c, DG_EUNSUPPORTED, "kinetic energy: axis-aligned elements only");
   return hip_check(c, dg::launch_kinetic_energy_grad(c->N, dev_mesh(c), c->dw, U, inv_volume(c), lam,
                                                      c->stream),
                    "kinetic energy gradient kernel");

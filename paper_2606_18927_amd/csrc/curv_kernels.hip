@@ -1,0 +1,546 @@
+// Split-form DGSEM on curvilinear hexahedra (FP64, periodic structured meshes).
+//
+// Geometry (the paper's production meshes are curved, Sec. 4): each element's
+// map is the degree-N interpolant of its node coordinates.  The metric terms
+// J a^i_n are Kopriva's conservative curl form,
+//   J a^i_n = -1/2 [curl_xi (X_l grad_xi X_m - X_m grad_xi X_l)]_i, (n, m, l) cyclic,
+// with the collocation derivative D for every xi-derivative, so the discrete
+// metric identities hold and both elements of a face see the same normal;
+// J = det(dX/dxi).  k_metrics computes them once per mesh into
+//   geo[c][e][node], c = 3 i + n: J a^i_n; c = 9: 1 / J.
+// Operator per stage (one workgroup per element, one lane per node; face
+// lanes = one lane per face node):
+//   k_face_flux_curv  BR1 gradients at the face nodes (chain rule with the
+//                     node's metrics: J grad q = sum_i J a^i (D_i q + lifting
+//                     term)) and the contravariant normal viscous flux
+//                     Fv^i = sum_d f_v,d J a^i_d of every face, to ffv;
+//   k_rhs_curv        gradients of every node, per direction i the
+//                     contravariant Kennedy-Gruber two-point flux with
+//                     averaged metrics sum_d f#_d (J a^i_d(A) + J a^i_d(B)) / 2
+//                     and the viscous flux Fv^i, Lax-Friedrichs across each
+//                     face with its normal J a^i (that of the element below
+//                     the face, shared by both sides), Ut = -(1/J)(...),
+//                     fused RK update.
+#include "dg_device.hpp"
+
+namespace dg {
+namespace {
+
+template <int N>
+struct CurvCfg {
+  static constexpr int NP = N + 1, NF = NP * NP, NN = NF * NP;
+  static constexpr int LANES = NN > 6 * NF ? NN : 6 * NF;
+  static constexpr int BS = (LANES + 63) / 64 * 64;
+};
+
+// sum_m D[idx][m] f(node with the dir-coordinate replaced by m), f an LDS field
+// indexed i + NP (j + NP k)
+template <int N>
+__device__ inline double dline(const double* f, const double (*sD)[N + 2], int dir, int i, int j,
+                               int k) {
+  constexpr int NP = N + 1;
+  const int idx = dir == 0 ? i : (dir == 1 ? j : k);
+  const int base = dir == 0 ? NP * (j + NP * k) : (dir == 1 ? i + NP * NP * k : i + NP * j);
+  const int step = dir == 0 ? 1 : (dir == 1 ? NP : NP * NP);
+  double a = 0.0;
+#pragma unroll
+  for (int m = 0; m < NP; ++m) a += sD[idx][m] * f[base + step * m];
+  return a;
+}
+
+// ---------------------------------------------------------------- metrics
+template <int N>
+__global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __restrict__ X,
+                                                           double* __restrict__ geo, DevBasis basis,
+                                                           long long nE, int* __restrict__ status) {
+  using C = CurvCfg<N>;
+  constexpr int NP = C::NP, NN = C::NN;
+  __shared__ double sD[NP][N + 2];
+  __shared__ double sX[3][NN];
+  __shared__ double sdX[9][NN];  // dX_n / dxi^j at 3 n + j
+  __shared__ double sV[3][NN];
+  const int tid = threadIdx.x;
+  const long long e = blockIdx.x;
+  const long long stride = nE * NN;
+  const bool active = tid < NN;
+  const int i = tid % NP, j = (tid / NP) % NP, k = tid / (NP * NP);
+  if (tid < NP * NP) sD[tid / NP][tid % NP] = basis.D[tid];
+  // coordinates relative to the element's node (0, 0, 0): the curl form is
+  // translation invariant, and its rounding then scales with the element's
+  // size instead of the magnitude of the coordinates
+  if (active) {
+#pragma unroll
+    for (int n = 0; n < 3; ++n) sX[n][tid] = X[n * stride + e * NN + tid] - X[n * stride + e * NN];
+  }
+  __syncthreads();
+  double dX[9];
+  if (active) {
+#pragma unroll
+    for (int n = 0; n < 3; ++n)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        dX[3 * n + d] = dline<N>(sX[n], sD, d, i, j, k);
+        sdX[3 * n + d][tid] = dX[3 * n + d];
+      }
+  }
+  __syncthreads();
+  double Ja[9];
+#pragma unroll
+  for (int n = 0; n < 3; ++n) {
+    const int m = (n + 1) % 3, l = (n + 2) % 3;
+    if (active) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        sV[d][tid] = sX[l][tid] * sdX[3 * m + d][tid] - sX[m][tid] * sdX[3 * l + d][tid];
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const int a = (r + 1) % 3, b = (r + 2) % 3;
+        Ja[3 * r + n] = -0.5 * (dline<N>(sV[b], sD, a, i, j, k) - dline<N>(sV[a], sD, b, i, j, k));
+      }
+    }
+    __syncthreads();
+  }
+  if (active) {
+    const double J = dX[0] * (dX[4] * dX[8] - dX[5] * dX[7]) - dX[1] * (dX[3] * dX[8] - dX[5] * dX[6]) +
+                     dX[2] * (dX[3] * dX[7] - dX[4] * dX[6]);
+    if (!(J > 0.0)) status[0] = 1;
+    const long long o = e * NN + tid;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) geo[c * stride + o] = Ja[c];
+    geo[9 * stride + o] = 1.0 / J;
+  }
+}
+
+// Own-side contravariant viscous flux along metric vector M from the stress:
+// (sum_d M_d tau_0d, sum_d M_d tau_1d, sum_d M_d tau_2d, u . (those) + M . qT)
+__device__ inline void contra_viscous(double u, double v, double w, const double tau[6],
+                                      const double qT[3], double M0, double M1, double M2,
+                                      double f[4]) {
+  f[0] = M0 * tau[0] + M1 * tau[3] + M2 * tau[4];
+  f[1] = M0 * tau[3] + M1 * tau[1] + M2 * tau[5];
+  f[2] = M0 * tau[4] + M1 * tau[5] + M2 * tau[2];
+  f[3] = u * f[0] + v * f[1] + w * f[2] + M0 * qT[0] + M1 * qT[1] + M2 * qT[2];
+}
+
+// Stress (t00, t11, t22, t01, t02, t12) and heat flux of physical gradients g[3 q + d]
+__device__ inline void stress64(const double g[12], double mu, double kappa, double tau[6],
+                                double qT[3]) {
+  const double dd = (2.0 / 3.0) * (g[0] + g[4] + g[8]);
+  tau[0] = mu * (g[0] + g[0] - dd);
+  tau[1] = mu * (g[4] + g[4] - dd);
+  tau[2] = mu * (g[8] + g[8] - dd);
+  tau[3] = mu * (g[1] + g[3]);
+  tau[4] = mu * (g[2] + g[6]);
+  tau[5] = mu * (g[5] + g[7]);
+  qT[0] = kappa * g[9];
+  qT[1] = kappa * g[10];
+  qT[2] = kappa * g[11];
+}
+
+// Physical gradients of q = (u, v, w, T) at node (i, j, k): reference
+// derivatives plus the lifting terms of the faces the node lies on, then
+// grad q = (1/J) sum_r J a^r gxi_r.  sq[c] are LDS fields of q; corr[f][c][ab]
+// the lifting terms (q* - q)(+-1/w) of face f.
+template <int N>
+__device__ inline void curv_gradients(const double* const sq[4], const double (*sD)[N + 2],
+                                      const double (*corr)[4][(N + 1) * (N + 1)], int i, int j, int k,
+                                      const double Ja[9], double invJ, double g[12]) {
+  constexpr int NP = N + 1;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double gx[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) gx[r] = dline<N>(sq[c], sD, r, i, j, k);
+    if (i == 0) gx[0] += corr[0][c][j + NP * k];
+    if (i == N) gx[0] += corr[1][c][j + NP * k];
+    if (j == 0) gx[1] += corr[2][c][i + NP * k];
+    if (j == N) gx[1] += corr[3][c][i + NP * k];
+    if (k == 0) gx[2] += corr[4][c][i + NP * j];
+    if (k == N) gx[2] += corr[5][c][i + NP * j];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g[3 * c + d] = invJ * (Ja[d] * gx[0] + Ja[3 + d] * gx[1] + Ja[6 + d] * gx[2]);
+  }
+}
+
+__device__ inline void load_geo(const double* geo, long long stride, long long idx, double Ja[9],
+                                double& invJ) {
+#pragma unroll
+  for (int c = 0; c < 9; ++c) Ja[c] = geo[c * stride + idx];
+  invJ = geo[9 * stride + idx];
+}
+
+// ---------------------------------------------------------- face viscous flux
+template <int N>
+__global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double* __restrict__ U,
+                                                                  double* __restrict__ ffv, DevMesh mesh,
+                                                                  DevPhys ph, DevBasis basis) {
+  using C = CurvCfg<N>;
+  constexpr int NP = C::NP, NF = C::NF, NN = C::NN;
+  __shared__ double sD[NP][N + 2];
+  __shared__ double sq[4][NN];
+  __shared__ double corr[6][4][NF];
+  const int tid = threadIdx.x;
+  const long long nE = mesh.nE;
+  const long long stride = nE * NN;
+  const long long e = xcd_remap(blockIdx.x, gridDim.x);
+  int ex, ey, ez;
+  elem_coords(e, mesh, ex, ey, ez);
+  if (tid < NP * NP) sD[tid / NP][tid % NP] = basis.D[tid];
+  if (tid < NN) {
+    double s[5];
+    load_state(U, stride, e * NN + tid, s);
+    const Prim P = primitives(s, ph);
+    sq[0][tid] = P.u;
+    sq[1][tid] = P.v;
+    sq[2][tid] = P.w;
+    sq[3][tid] = P.T;
+  }
+  if (tid < 6 * NF) {
+    const FaceTask<N> ft(tid);
+    const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
+    double so[5], sn[5];
+    load_state(U, stride, e * NN + ft.own_node(), so);
+    load_state(U, stride, nb * NN + ft.nb_node(), sn);
+    const Prim Po = primitives(so, ph), Pn = primitives(sn, ph);
+    const double qo[4] = {Po.u, Po.v, Po.w, Po.T}, qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
+    const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (0.5 * (qo[c] + qn[c]) - qo[c]) * sc;
+  }
+  __syncthreads();
+  if (tid >= NN) return;
+  const int i = tid % NP, j = (tid / NP) % NP, k = tid / NF;
+  const bool on_face = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
+  if (!on_face) return;
+  double Ja[9], invJ;
+  load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
+  const double* const q[4] = {sq[0], sq[1], sq[2], sq[3]};
+  double g[12];
+  curv_gradients<N>(q, sD, corr, i, j, k, Ja, invJ, g);
+  const double r = viscosity_ratio(ph, sq[3][tid]);
+  double tau[6], qT[3];
+  stress64(g, ph.mu * r, ph.kappa * r, tau, qT);
+  const double u = sq[0][tid], v = sq[1][tid], w = sq[2][tid];
+  double* out = ffv + e * (6 * 4 * NF);
+  double f[4];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int idx = d == 0 ? i : (d == 1 ? j : k);
+    if (idx != 0 && idx != N) continue;
+    const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
+    const int fi = 2 * d + (idx == N ? 1 : 0);
+    contra_viscous(u, v, w, tau, qT, Ja[3 * d], Ja[3 * d + 1], Ja[3 * d + 2], f);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) out[(fi * 4 + c) * NF + ab] = f[c];
+  }
+}
+
+// ------------------------------------------------------- right-hand side / RK
+template <int N, bool RK, bool VISC>
+__global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
+    const double* __restrict__ U, const double* __restrict__ ffv, double* __restrict__ out,
+    double* __restrict__ U_out, DevMesh mesh, DevPhys ph, DevBasis basis, Stage st,
+    int* __restrict__ status) {
+  using C = CurvCfg<N>;
+  constexpr int NP = C::NP, NF = C::NF, NN = C::NN;
+  __shared__ double sD[NP][N + 2];
+  __shared__ double sp[6][NN];            // rho, u, v, w, p, e
+  __shared__ double sX[6][5][NF];         // own viscous face flux, then surface terms
+  // phase-shared regions: (T, lifting terms) until the gradients are formed,
+  // (viscous flux, metric of the sweep direction) in the sweeps
+  constexpr int R1 = NN + 6 * 4 * NF, R2 = 4 * NN + 3 * NN;
+  __shared__ double sbuf[R1 > R2 ? R1 : R2];
+  double* sT = sbuf;
+  double(*corr)[4][NF] = reinterpret_cast<double(*)[4][NF]>(sbuf + NN);
+  double(*sfv)[NN] = reinterpret_cast<double(*)[NN]>(sbuf);
+  double(*sM)[NN] = reinterpret_cast<double(*)[NN]>(sbuf + 4 * NN);
+
+  const int tid = threadIdx.x;
+  const long long nE = mesh.nE;
+  const long long stride = nE * NN;
+  const long long e = xcd_remap(blockIdx.x, gridDim.x);
+  int ex, ey, ez;
+  elem_coords(e, mesh, ex, ey, ez);
+  const bool active = tid < NN;
+  const bool face_lane = tid < 6 * NF;
+  const int i = tid % NP, j = (tid / NP) % NP, k = tid / NF;
+  if (tid < NP * NP) sD[tid / NP][tid % NP] = basis.D[tid];
+
+  // P1: own state and metrics; face lanes fetch the neighbour's face node
+  double u0[5] = {1.0, 0.0, 0.0, 0.0, 1.0}, Ja[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, invJ = 0.0;
+  double A[6] = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
+  if (active) {
+    load_state(U, stride, e * NN + tid, u0);
+    load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
+  }
+  double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  long long nb = 0;
+  if (face_lane) {
+    const FaceTask<N> ft(tid);
+    nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
+    load_state(U, stride, nb * NN + ft.nb_node(), sn);
+  }
+  if (active) {
+    const Prim P = primitives(u0, ph);
+    if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
+    A[0] = P.rho; A[1] = P.u; A[2] = P.v; A[3] = P.w; A[4] = P.p; A[5] = P.e;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sp[c][tid] = A[c];
+    if (VISC) sT[tid] = P.T;
+  }
+  __syncthreads();
+
+  // P1b: BR1 lifting terms of the face nodes
+  if (VISC) {
+    if (face_lane) {
+      const FaceTask<N> ft(tid);
+      const int lo = ft.own_node();
+      const double qo[4] = {sp[1][lo], sp[2][lo], sp[3][lo], sT[lo]};
+      const Prim Pn = primitives(sn, ph);
+      const double qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
+      const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (0.5 * (qo[c] + qn[c]) - qo[c]) * sc;
+    }
+    __syncthreads();
+  }
+
+  // P2: gradients, stress and heat flux
+  double tau[6] = {0, 0, 0, 0, 0, 0}, qT[3] = {0, 0, 0};
+  if (VISC) {
+    if (active) {
+      const double* const q[4] = {sp[1], sp[2], sp[3], sT};
+      double g[12];
+      curv_gradients<N>(q, sD, corr, i, j, k, Ja, invJ, g);
+      const double r = viscosity_ratio(ph, sT[tid]);
+      stress64(g, ph.mu * r, ph.kappa * r, tau, qT);
+    }
+    __syncthreads();
+  }
+
+  // P3: per direction, volume sweep of the two-point and viscous fluxes
+  double ut[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int idx = d == 0 ? i : (d == 1 ? j : k);
+    const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
+    const double M0 = Ja[3 * d], M1 = Ja[3 * d + 1], M2 = Ja[3 * d + 2];
+    if (active) {
+      sM[0][tid] = M0;
+      sM[1][tid] = M1;
+      sM[2][tid] = M2;
+      if (VISC) {
+        double f[4];
+        contra_viscous(A[1], A[2], A[3], tau, qT, M0, M1, M2, f);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sfv[c][tid] = f[c];
+        if (idx == 0 || idx == N) {
+          const int fi = 2 * d + (idx == N ? 1 : 0);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) sX[fi][c][ab] = f[c];
+        }
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const int base = d == 0 ? NP * (j + NP * k) : (d == 1 ? i + NF * k : i + NP * j);
+      const int step = d == 0 ? 1 : (d == 1 ? NP : NF);
+      double ac[5] = {0, 0, 0, 0, 0}, av[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int m = 0; m < NP; ++m) {
+        const int nm = base + step * m;
+        const double Dm = sD[idx][m];
+        const double rho = 0.5 * (A[0] + sp[0][nm]);
+        const double uu = 0.5 * (A[1] + sp[1][nm]);
+        const double vv = 0.5 * (A[2] + sp[2][nm]);
+        const double ww = 0.5 * (A[3] + sp[3][nm]);
+        const double pp = 0.5 * (A[4] + sp[4][nm]);
+        const double ee = 0.5 * (A[5] + sp[5][nm]);
+        const double m0 = 0.5 * (M0 + sM[0][nm]), m1 = 0.5 * (M1 + sM[1][nm]), m2 = 0.5 * (M2 + sM[2][nm]);
+        const double Uc = uu * m0 + vv * m1 + ww * m2;
+        const double mass = rho * Uc;
+        ac[0] += Dm * mass;
+        ac[1] += Dm * (mass * uu + pp * m0);
+        ac[2] += Dm * (mass * vv + pp * m1);
+        ac[3] += Dm * (mass * ww + pp * m2);
+        ac[4] += Dm * (mass * ee + pp * Uc);
+        if (VISC) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) av[c] += Dm * sfv[c][nm];
+        }
+      }
+      ut[0] -= 2.0 * ac[0];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) ut[1 + c] -= 2.0 * ac[1 + c] - av[c];
+    }
+    __syncthreads();
+  }
+
+  double gA[5] = {0, 0, 0, 0, 0};
+  if (RK && active && st.read_G) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
+  }
+
+  // P4: surface terms (face lanes)
+  if (face_lane) {
+    const FaceTask<N> ft(tid);
+    const int lo = ft.own_node();
+    // one normal per face: that of the element below it (own on an upper face,
+    // the neighbour's on a lower face), so the two sides' fluxes are exact
+    // negatives even where the face nodes of the two elements differ in
+    // rounding (the periodic seam)
+    double s[3];
+    const long long gi = ft.up ? e * NN + lo : nb * NN + ft.nb_node();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] = mesh.geo[(3 * ft.d + c) * stride + gi];
+    const double Ao[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
+    const Prim Pn = primitives(sn, ph);
+    const double An[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
+    const double so[5] = {Ao[0], Ao[0] * Ao[1], Ao[0] * Ao[2], Ao[0] * Ao[3], Ao[0] * Ao[5]};
+    // own contravariant Euler flux
+    const double Uo = Ao[1] * s[0] + Ao[2] * s[1] + Ao[3] * s[2];
+    const double Fo[5] = {Ao[0] * Uo, Ao[0] * Ao[1] * Uo + Ao[4] * s[0], Ao[0] * Ao[2] * Uo + Ao[4] * s[1],
+                          Ao[0] * Ao[3] * Uo + Ao[4] * s[2], (Ao[0] * Ao[5] + Ao[4]) * Uo};
+    // central part: the contravariant Kennedy-Gruber flux of the two sides
+    const double rho = 0.5 * (Ao[0] + An[0]), uu = 0.5 * (Ao[1] + An[1]), vv = 0.5 * (Ao[2] + An[2]);
+    const double ww = 0.5 * (Ao[3] + An[3]), pp = 0.5 * (Ao[4] + An[4]), ee = 0.5 * (Ao[5] + An[5]);
+    const double Uc = uu * s[0] + vv * s[1] + ww * s[2];
+    const double mass = rho * Uc;
+    double Fs[5] = {mass, mass * uu + pp * s[0], mass * vv + pp * s[1], mass * ww + pp * s[2],
+                    mass * ee + pp * Uc};
+    if (!ph.central) {
+      const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+      const double co = sqrt(ph.gamma * Ao[4] / Ao[0]), cn = sqrt(ph.gamma * An[4] / An[0]);
+      const double uno = Uo / smag, unn = (An[1] * s[0] + An[2] * s[1] + An[3] * s[2]) / smag;
+      // L = own on an upper face, the neighbour on a lower face; ties go to L
+      const double lo_l = ft.up ? fabs(uno) + co : fabs(unn) + cn;
+      const double lo_r = ft.up ? fabs(unn) + cn : fabs(uno) + co;
+      const double lam = lo_r > lo_l ? lo_r : lo_l;
+      const double h = 0.5 * lam * smag * (ft.up ? 1.0 : -1.0);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) Fs[v] -= h * (sn[v] - so[v]);
+    }
+    double fvo[4] = {0, 0, 0, 0}, fvs[4] = {0, 0, 0, 0};
+    if (VISC) {
+      const double* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        fvo[c] = sX[ft.f][c][ft.ab];
+        fvs[c] = 0.5 * (fvo[c] + src[c * NF]);
+      }
+    }
+    const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
+    double corr5[5];
+    corr5[0] = sc * (Fs[0] - Fo[0]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) corr5[1 + c] = sc * ((Fs[1 + c] - fvs[c]) - (Fo[1 + c] - fvo[c]));
+#pragma unroll
+    for (int v = 0; v < 5; ++v) sX[ft.f][v][ft.ab] = corr5[v];
+  }
+  __syncthreads();
+
+  // P5: surface terms, 1/J, output
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      double c = 0.0;
+      if (i == 0) c += sX[0][v][j + NP * k];
+      if (i == N) c += sX[1][v][j + NP * k];
+      if (j == 0) c += sX[2][v][i + NP * k];
+      if (j == N) c += sX[3][v][i + NP * k];
+      if (k == 0) c += sX[4][v][i + NP * j];
+      if (k == N) c += sX[5][v][i + NP * j];
+      ut[v] = invJ * (ut[v] - c);
+    }
+    const long long idx = e * NN + tid;
+    if (RK) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        const double gv = st.A * gA[v] + st.dt * ut[v];
+        out[v * stride + idx] = gv;
+        U_out[v * stride + idx] = u0[v] + st.B * gv;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) out[v * stride + idx] = ut[v];
+    }
+  }
+}
+
+template <int N>
+hipError_t metrics_n(const double* X, double* geo, const DevBasis& b, long long nE, int* status,
+                     hipStream_t s) {
+  hipLaunchKernelGGL((k_metrics<N>), dim3(static_cast<unsigned>(nE)), dim3(CurvCfg<N>::BS), 0, s, X, geo, b,
+                     nE, status);
+  return hipGetLastError();
+}
+
+template <int N>
+hipError_t face_flux_curv_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
+                            double* ffv, hipStream_t s) {
+  hipLaunchKernelGGL((k_face_flux_curv<N>), dim3(static_cast<unsigned>(m.nE)), dim3(CurvCfg<N>::BS), 0, s, U,
+                     ffv, m, p, b);
+  return hipGetLastError();
+}
+
+template <int N, bool RK>
+hipError_t rhs_curv_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
+                      const double* ffv, double* out, double* U_out, const Stage& st, int* status,
+                      hipStream_t s) {
+  const dim3 grid(static_cast<unsigned>(m.nE)), block(CurvCfg<N>::BS);
+  if (p.viscous)
+    hipLaunchKernelGGL((k_rhs_curv<N, RK, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st, status);
+  else
+    hipLaunchKernelGGL((k_rhs_curv<N, RK, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st, status);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_metrics(int N, const double* X, double* geo, const DevBasis& b, long long nE,
+                          int* status, hipStream_t s) {
+  switch (N) {
+    case 3: return metrics_n<3>(X, geo, b, nE, status, s);
+    case 5: return metrics_n<5>(X, geo, b, nE, status, s);
+    case 7: return metrics_n<7>(X, geo, b, nE, status, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_face_flux_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                 const double* U, double* ffv, hipStream_t s) {
+  switch (N) {
+    case 3: return face_flux_curv_n<3>(m, p, b, U, ffv, s);
+    case 5: return face_flux_curv_n<5>(m, p, b, U, ffv, s);
+    case 7: return face_flux_curv_n<7>(m, p, b, U, ffv, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rhs_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                           const double* U, const double* ffv, double* Ut, int* status, hipStream_t s) {
+  const Stage st{0.0, 0.0, 0.0, 0};
+  switch (N) {
+    case 3: return rhs_curv_n<3, false>(m, p, b, U, ffv, Ut, nullptr, st, status, s);
+    case 5: return rhs_curv_n<5, false>(m, p, b, U, ffv, Ut, nullptr, st, status, s);
+    case 7: return rhs_curv_n<7, false>(m, p, b, U, ffv, Ut, nullptr, st, status, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rk_stage_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                const double* U, const double* ffv, double* G, double* U_out,
+                                const Stage& st, int* status, hipStream_t s) {
+  switch (N) {
+    case 3: return rhs_curv_n<3, true>(m, p, b, U, ffv, G, U_out, st, status, s);
+    case 5: return rhs_curv_n<5, true>(m, p, b, U, ffv, G, U_out, st, status, s);
+    case 7: return rhs_curv_n<7, true>(m, p, b, U, ffv, G, U_out, st, status, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace dg

@@ -23,6 +23,7 @@ struct DevMesh {
   const double* s[3]; // device tables of s_d per element index along d
   long long nE;       // number of elements
   const double* tauw; // wall-model stress per wall-face node (DG_BC_WALL_MODEL), or null
+  const double* geo;  // curvilinear metrics geo[c][e][node] (c = 3 i + n: J a^i_n; 9: 1/J), or null
 };
 
 // Gas constants and switches (FP64; kernels cast where they compute in FP32).
@@ -75,6 +76,19 @@ hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBa
 // y = a y + b x over n doubles.
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
+// Curvilinear hexahedra (curv_kernels.hip, FP64): metric terms from the node
+// coordinates X[n][e][node] (status[0] = 1 where J <= 0), and the operator
+// (face viscous fluxes double*, one RK stage or the right-hand side alone).
+hipError_t launch_metrics(int N, const double* X, double* geo, const DevBasis& b, long long nE,
+                          int* status, hipStream_t s);
+hipError_t launch_face_flux_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                 const double* U, double* ffv, hipStream_t s);
+hipError_t launch_rhs_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                           const double* U, const double* ffv, double* Ut, int* status, hipStream_t s);
+hipError_t launch_rk_stage_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                const double* U, const double* ffv, double* G, double* U_out,
+                                const Stage& st, int* status, hipStream_t s);
+
 // Wall-stress model: number of wall faces of the mesh, and the kernel (one
 // lane per wall-face node).
 long long wall_faces(const DevMesh& m);
@@ -105,6 +119,9 @@ struct dg_ctx {
   int wm_node = 1;            // interface node of the wall model
   bool wall_model = false;    // some direction has DG_BC_WALL_MODEL ends
   double* tauw = nullptr;     // wall stress of the current stage (workspace)
+  bool curvilinear = false;   // node coordinates given: curved elements
+  std::vector<double> nodes;  // their host copy [n][e][node]
+  double* geo = nullptr;      // metric terms (workspace)
   long long n_wall_faces = 0;
   dg_physics phys{};
   hipStream_t stream = nullptr;

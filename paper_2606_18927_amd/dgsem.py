@@ -37,7 +37,8 @@ class DgsemError(RuntimeError):
 class MeshDesc(ctypes.Structure):
     _fields_ = [("N", ctypes.c_int), ("nelem", ctypes.c_int * 3),
                 ("faces", ctypes.POINTER(ctypes.c_double) * 3), ("bc", ctypes.c_int * 3),
-                ("T_wall", ctypes.c_double), ("wm_node", ctypes.c_int)]
+                ("T_wall", ctypes.c_double), ("wm_node", ctypes.c_int),
+                ("nodes", ctypes.POINTER(ctypes.c_double))]
 
 
 class Physics(ctypes.Structure):
@@ -137,9 +138,13 @@ class MeshSpec:
     bc: tuple = ("periodic", "periodic", "periodic")
     T_wall: float = 1.0
     wm_node: int = 1           # interface node of "wallmodel" ends
+    nodes: object = None       # curved elements: node coordinates (3, nz, ny, nx, N+1, N+1, N+1)
 
     @property
     def nelem(self):
+        if self.faces is None:
+            nz, ny, nx = np.shape(self.nodes)[1:4]
+            return (nx, ny, nz)
         return tuple(len(f) - 1 for f in self.faces)
 
 
@@ -155,13 +160,23 @@ class Solver:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.current_stream(self.device)
         self.mesh = mesh
-        self._faces = [np.ascontiguousarray(f, dtype=np.float64) for f in mesh.faces]
+        self._faces = None if mesh.faces is None else \
+            [np.ascontiguousarray(f, dtype=np.float64) for f in mesh.faces]
         desc = MeshDesc()
         desc.N = mesh.N
+        nelem = mesh.nelem
         for d in range(3):
-            desc.nelem[d] = len(self._faces[d]) - 1
-            desc.faces[d] = self._faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            desc.nelem[d] = nelem[d]
+            if self._faces is not None:
+                desc.faces[d] = self._faces[d].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             desc.bc[d] = BC[mesh.bc[d]]
+        self._nodes = None
+        if mesh.nodes is not None:
+            NP = mesh.N + 1
+            self._nodes = np.ascontiguousarray(mesh.nodes, dtype=np.float64).reshape(-1)
+            if self._nodes.size != 3 * nelem[0] * nelem[1] * nelem[2] * NP ** 3:
+                raise ValueError("nodes must hold 3 coordinates per node")
+            desc.nodes = self._nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         desc.T_wall = mesh.T_wall
         desc.wm_node = mesh.wm_node
         T_ref, S = sutherland if sutherland is not None else (0.0, 0.0)
@@ -314,7 +329,9 @@ class Solver:
 def solver_for(workload, *, device=None, with_adjoint=False, precision=None, viscous=True,
                central_only=False, flux=None) -> Solver:
     """Solver for a paper_2606_18927_amd.workloads.Workload."""
-    mesh = MeshSpec(workload.N, workload.faces(), workload.bc, workload.T_wall, workload.wm_node)
+    nodes = workload.nodes(lgl(workload.N)[0]) if workload.warp else None
+    mesh = MeshSpec(workload.N, None if nodes is not None else workload.faces(), workload.bc, workload.T_wall,
+                    workload.wm_node, nodes)
     return Solver(mesh, workload.gamma, workload.R, workload.mu, workload.Pr, viscous=viscous,
                   precision=precision or workload.precision, central_only=central_only,
                   flux=flux or workload.flux, sutherland=workload.sutherland,

@@ -62,6 +62,7 @@ class Workload:
     wall: str = "wall"        # channel ends: "wall" (isothermal) | "wallmodel" (slip, modelled stress)
     wm_node: int = 1          # interface LGL node of "wallmodel" ends
     sutherland: tuple | None = None  # (T_ref, S) of Sutherland's law; None: constant viscosity
+    warp: float = 0.0         # > 0: curved elements, the periodic warped box of warped_nodes(amp=warp)
     extra: dict = field(default_factory=dict)
 
     # gas / physics parameters -------------------------------------------
@@ -99,6 +100,13 @@ class Workload:
             return channel_faces(nx, ny, nz)
         return tgv_faces(nx), tgv_faces(ny), tgv_faces(nz)
 
+    def nodes(self, xi):
+        """Node coordinates (3, nz, ny, nx, NP, NP, NP) of a curved workload, else None."""
+        if not self.warp:
+            return None
+        lengths = tuple(float(f[-1] - f[0]) for f in self.faces())
+        return warped_nodes(xi, self.nelem, lengths, self.warp)
+
     @property
     def n_dof(self) -> int:
         nx, ny, nz = self.nelem
@@ -120,6 +128,11 @@ WORKLOADS = {
     "tgv_n7_32x32x32_sutherland": Workload("tgv_n7_32x32x32_sutherland", "tgv", 7, (32, 32, 32),
                                            nsteps=100, noise=0.01, seed=TGV_SEED,
                                            sutherland=(1.0, 110.4 / 288.15)),
+    # the same on curved elements: the periodic box warped by 5 % of its size
+    "tgv_n7_32x32x32_curved": Workload("tgv_n7_32x32x32_curved", "tgv", 7, (32, 32, 32), nsteps=100,
+                                       noise=0.01, seed=TGV_SEED, warp=0.05),
+    # small curved Taylor-Green case for full oracle comparisons
+    "tgv_n3_4x4x4_curved": Workload("tgv_n3_4x4x4_curved", "tgv", 3, (4, 4, 4), nsteps=10, warp=0.05),
     # stretched channel for the adjoint: N=5, 16^3 elements, 50 steps
     "channel_n5_16x16x16": Workload("channel_n5_16x16x16", "channel", 5, (16, 16, 16),
                                     nsteps=50, seed=CHANNEL_SEED),
@@ -199,7 +212,7 @@ def _widths(faces):
 
 
 def _prim_state(wl: Workload, xi):
-    X, Y, Z = node_coords(xi, wl.faces())
+    X, Y, Z = node_coords(xi, wl.faces()) if not wl.warp else tuple(wl.nodes(xi))
     gamma = wl.gamma
     if wl.kind == "tgv":
         p0 = 1.0 / (gamma * wl.Ma ** 2)

@@ -158,3 +158,46 @@ def test_wall_face_count(L):
         # device call without a workspace is refused before any HIP call
         assert L.dg_wall_stress(ctx, None, 1, None) == dgsem.DG_ESTATE
         L.dg_free(ctx)
+
+
+def test_curved_mesh_validation(L):
+    """Curved elements (node coordinates given): periodic, FP64, Kennedy-Gruber
+    only; faces may be absent; non-finite coordinates are rejected.  Host only."""
+    from paper_2606_18927_amd.workloads import warped_nodes
+    N, n = 3, (2, 2, 2)
+    X = np.ascontiguousarray(warped_nodes(dgsem.lgl(N)[0], n)).reshape(-1)
+
+    def desc(bc=(0, 0, 0), nodes=X, with_faces=False):
+        d, keep = _desc(N=N, n=n, bc=bc)
+        if not with_faces:
+            for k in range(3):
+                d.faces[k] = ctypes.POINTER(ctypes.c_double)()
+        d.nodes = nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        return d, keep
+
+    d, keep = desc()
+    st, ctx = _init(L, d, _phys())
+    assert st == dgsem.DG_OK
+    size = ctypes.c_size_t()
+    assert L.dg_workspace_bytes(ctx, 0, ctypes.byref(size)) == dgsem.DG_OK
+    L.dg_free(ctx)
+    d0, keep0 = _desc(N=N, n=n)
+    plain = ctypes.c_size_t()
+    st, ctx = _init(L, d0, _phys())
+    L.dg_workspace_bytes(ctx, 0, ctypes.byref(plain))
+    L.dg_free(ctx)
+    nd = 8 * 64
+    assert size.value >= plain.value + 10 * nd * 8  # metric terms: 10 values per DOF
+    for bad, code in ((dict(precision=1), dgsem.DG_EUNSUPPORTED), (dict(flux=1), dgsem.DG_EUNSUPPORTED)):
+        d, keep = desc()
+        assert _init(L, d, _phys(**bad))[0] == code, bad
+    d, keep = desc(bc=(0, 1, 0))
+    assert _init(L, d, _phys())[0] == dgsem.DG_EUNSUPPORTED
+    Xn = X.copy()
+    Xn[17] = np.nan
+    d, keep = desc(nodes=Xn)
+    assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL
+    # faces are still required without node coordinates
+    d, keep = _desc(N=N, n=n)
+    d.faces[1] = ctypes.POINTER(ctypes.c_double)()
+    assert _init(L, d, _phys())[0] == dgsem.DG_EINVAL
