@@ -14,6 +14,8 @@ paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
   ec_roe        the same step with the entropy-conserving volume flux and the
                 Roe surface flux (FP64);
   sutherland    the same step with Sutherland's viscosity law (FP64);
+  curved        the same step on curved elements (the periodic box warped by
+                5 %, FP64): per-node metric terms, contravariant fluxes;
   wall_model    the N = 5, 48x32x48 channel with wall-modelled slip walls and
                 Sutherland's law (FP64) beside the same channel with
                 isothermal walls and constant viscosity, and the wall-stress
@@ -55,7 +57,7 @@ STORED_GRADIENT_BYTES_PER_DOF = 392.0
 
 # HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
 # counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
-# 128 x 14,203,649.3 TCC_EA0_RDREQ_128B + 64 x 2,372.3 RDREQ_64B, writes
+# 128 x 14,195,619.6 TCC_EA0_RDREQ_128B + 64 x 2,531.5 RDREQ_64B, writes
 # WRITE_SIZE 1,310,720 KiB.  Valid only for the kernel sources it was counted
 # on; reported as null once they change.
 COUNTED_TRAFFIC = {"sources_sha256_prefix": "fdc55d6dc7c59187", "bytes_per_launch": 3159378607.0}
@@ -83,6 +85,7 @@ def _parse():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-ec", action="store_true", help="skip the entropy-conserving / Roe flux leg")
+    ap.add_argument("--no-curved", action="store_true", help="skip the curved-element leg")
     ap.add_argument("--no-physics", action="store_true",
                     help="skip the Sutherland and wall-model legs")
     ap.add_argument("--adjoint-steps", type=int, default=50)
@@ -110,6 +113,49 @@ def _leg(wl_name, r):
     return {"workload": wl_name, "ns_per_dof_stage": r["ns_per_dof_stage"], "ms_per_step": r["ms_per_step"],
             "rk_kernel_ms": r["rk_kernel_ms"], "face_kernel_ms": r["face_kernel_ms"],
             "step_alg_gbs": r["step_alg_gbs"], "step_frac": r["step_alg_gbs"] / HBM_PEAK_GBS}
+
+
+def curved_alg_bytes(N: int = 7):
+    """Algorithmic bytes per DOF and stage of the curved-element kernels (FP64):
+    k_rhs_curv reads U 40, the neighbours' face fluxes 24 (6 (N+1)^2 faces x 4
+    values per element), G 40 (not on stage 1) and the metric terms 80 (J a^i_n
+    and 1/J), and writes G and U (80); k_face_flux_curv reads U 40 and the
+    metric terms of the face nodes only, and writes the face fluxes."""
+    NP = N + 1
+    ff = 24.0 / NP * 8
+    face_nodes = 2 * NP * NP + (N - 1) * 4 * N
+    return {"face": 40 + 80.0 * face_nodes / NP ** 3 + ff, "rk": 40 + ff + 40 + 80 + 80,
+            "rk_first": 40 + ff + 80 + 80}
+
+
+def run_curved(steps, warmup):
+    """The Taylor-Green step on the warped (curved) N = 7, 32^3 mesh, FP64."""
+    import torch
+
+    from paper_2606_18927_amd import dgsem, workloads
+    wl = workloads.WORKLOADS["tgv_n7_32x32x32_curved"]
+    xi, _ = dgsem.lgl(wl.N)
+    U, dt = workloads.make_state(wl, xi)
+    S = dgsem.solver_for(wl)
+    S.set_state(torch.as_tensor(U.reshape(-1)).cuda())
+    del U
+    ms, lift_ms, rk_ms, n_lift, n_rk = time_steps(S, dt, steps, warmup)
+    dof, stages = S.n_dof, steps * 5
+    b = curved_alg_bytes(wl.N)
+    rk_bytes = dof * (b["rk"] * (stages - steps) + b["rk_first"] * steps) / stages
+    rk_s = rk_ms / 1e3 / n_rk
+    face_s = lift_ms / 1e3 / max(n_lift, 1)
+    step_bytes = dof * (b["face"] * stages + b["rk"] * (stages - steps) + b["rk_first"] * steps)
+    out = {"workload": wl.name, "warp": wl.warp, "ns_per_dof_stage": ms * 1e6 / (dof * stages),
+           "ms_per_step": ms / steps, "rk_kernel": "k_rhs_curv", "rk_kernel_ms": rk_ms / n_rk,
+           "face_kernel_ms": lift_ms / max(n_lift, 1), "rk_bytes_per_launch": rk_bytes,
+           "rk_kernel_gbs": rk_bytes / rk_s / 1e9, "rk_frac": rk_bytes / rk_s / 1e9 / HBM_PEAK_GBS,
+           "face_kernel_gbs": dof * b["face"] / face_s / 1e9,
+           "step_alg_bytes_per_dof": step_bytes / (dof * stages), "step_alg_gbs": step_bytes / (ms / 1e3) / 1e9,
+           "step_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    del S
+    torch.cuda.empty_cache()
+    return out
 
 
 def run_wall_model(steps, warmup):
@@ -359,6 +405,15 @@ def main():
                   flush=True)
         except dgsem.DgsemError as e:
             wall = {"error": str(e)}
+    curved = None
+    if not args.no_curved and wl.name == "tgv_n7_32x32x32":
+        try:
+            curved = run_curved(args.steps, args.warmup)
+            print(f"[bench] curved {curved['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage, k_rhs_curv "
+                  f"{curved['rk_kernel_ms']*1e3:.0f} us ({curved['rk_frac']*100:.0f} % of HBM)", file=sys.stderr,
+                  flush=True)
+        except dgsem.DgsemError as e:
+            curved = {"error": str(e)}
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint(args.adjoint_steps, 25)
@@ -411,6 +466,7 @@ def main():
         "mixed": mixed,
         "ec_roe": ec,
         "sutherland": suth,
+        "curved": curved,
         "wall_model": wall,
         "adjoint": adjoint,
         "context_mi300a_pid_ns": {"range": [2.457, 4.260], "note": "paper Table 1, 32 APUs, N=7 free stream"},

@@ -240,7 +240,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
 
 // ------------------------------------------------------- right-hand side / RK
 template <int N, bool RK, bool VISC>
-__global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
+__global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs_curv(
     const double* __restrict__ U, const double* __restrict__ ffv, double* __restrict__ out,
     double* __restrict__ U_out, DevMesh mesh, DevPhys ph, DevBasis basis, Stage st,
     int* __restrict__ status) {
@@ -269,28 +269,29 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
   const int i = tid % NP, j = (tid / NP) % NP, k = tid / NF;
   if (tid < NP * NP) sD[tid / NP][tid % NP] = basis.D[tid];
 
-  // P1: own state and metrics; face lanes fetch the neighbour's face node
-  double u0[5] = {1.0, 0.0, 0.0, 0.0, 1.0}, Ja[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, invJ = 0.0;
-  double A[6] = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
-  if (active) {
-    load_state(U, stride, e * NN + tid, u0);
-    load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
-  }
-  double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  // P1: own state; face lanes fetch the neighbour's face node (registers are
+  // the limit of this kernel: metric terms, the neighbour's state and the own
+  // primitives are fetched again where they are used, from L2 and LDS)
   long long nb = 0;
   if (face_lane) {
     const FaceTask<N> ft(tid);
     nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
-    load_state(U, stride, nb * NN + ft.nb_node(), sn);
   }
   if (active) {
+    double u0[5];
+    load_state(U, stride, e * NN + tid, u0);
     const Prim P = primitives(u0, ph);
     if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
-    A[0] = P.rho; A[1] = P.u; A[2] = P.v; A[3] = P.w; A[4] = P.p; A[5] = P.e;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) sp[c][tid] = A[c];
+    sp[0][tid] = P.rho;
+    sp[1][tid] = P.u;
+    sp[2][tid] = P.v;
+    sp[3][tid] = P.w;
+    sp[4][tid] = P.p;
+    sp[5][tid] = P.e;
     if (VISC) sT[tid] = P.T;
   }
+  double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  if (VISC && face_lane) load_state(U, stride, nb * NN + FaceTask<N>(tid).nb_node(), sn);
   __syncthreads();
 
   // P1b: BR1 lifting terms of the face nodes
@@ -312,6 +313,8 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
   double tau[6] = {0, 0, 0, 0, 0, 0}, qT[3] = {0, 0, 0};
   if (VISC) {
     if (active) {
+      double Ja[9], invJ;
+      load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
       const double* const q[4] = {sp[1], sp[2], sp[3], sT};
       double g[12];
       curv_gradients<N>(q, sD, corr, i, j, k, Ja, invJ, g);
@@ -323,12 +326,18 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
 
   // P3: per direction, volume sweep of the two-point and viscous fluxes
   double ut[5] = {0, 0, 0, 0, 0};
-#pragma unroll
+#pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     const int idx = d == 0 ? i : (d == 1 ? j : k);
     const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
-    const double M0 = Ja[3 * d], M1 = Ja[3 * d + 1], M2 = Ja[3 * d + 2];
+    double M0 = 0.0, M1 = 0.0, M2 = 0.0, A[6] = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     if (active) {
+      const long long gi = e * NN + tid;
+      M0 = mesh.geo[(3 * d) * stride + gi];
+      M1 = mesh.geo[(3 * d + 1) * stride + gi];
+      M2 = mesh.geo[(3 * d + 2) * stride + gi];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) A[c] = sp[c][tid];
       sM[0][tid] = M0;
       sM[1][tid] = M1;
       sM[2][tid] = M2;
@@ -379,11 +388,6 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
     __syncthreads();
   }
 
-  double gA[5] = {0, 0, 0, 0, 0};
-  if (RK && active && st.read_G) {
-#pragma unroll
-    for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
-  }
 
   // P4: surface terms (face lanes)
   if (face_lane) {
@@ -398,6 +402,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
 #pragma unroll
     for (int c = 0; c < 3; ++c) s[c] = mesh.geo[(3 * ft.d + c) * stride + gi];
     const double Ao[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
+    load_state(U, stride, nb * NN + ft.nb_node(), sn);
     const Prim Pn = primitives(sn, ph);
     const double An[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
     const double so[5] = {Ao[0], Ao[0] * Ao[1], Ao[0] * Ao[2], Ao[0] * Ao[3], Ao[0] * Ao[5]};
@@ -445,6 +450,12 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
 
   // P5: surface terms, 1/J, output
   if (active) {
+    double gA[5] = {0, 0, 0, 0, 0};
+    const double invJ = mesh.geo[9 * stride + e * NN + tid];
+    if (RK && st.read_G) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
+    }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
       double c = 0.0;
@@ -458,6 +469,8 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_rhs_curv(
     }
     const long long idx = e * NN + tid;
     if (RK) {
+      double u0[5];
+      load_state(U, stride, idx, u0);  // read again: holding it from P1 spills
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double gv = st.A * gA[v] + st.dt * ut[v];
