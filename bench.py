@@ -57,22 +57,27 @@ STORED_GRADIENT_BYTES_PER_DOF = 392.0
 
 # HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
 # counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
-# 128 x 14,195,619.6 TCC_EA0_RDREQ_128B + 64 x 2,531.5 RDREQ_64B, writes
+# 128 x 14,193,157.5 TCC_EA0_RDREQ_128B + 64 x 2,511.8 RDREQ_64B, writes
 # WRITE_SIZE 1,310,720 KiB.  Valid only for the kernel sources it was counted
 # on; reported as null once they change.
-COUNTED_TRAFFIC = {"sources_sha256_prefix": "fdc55d6dc7c59187", "bytes_per_launch": 3159378607.0}
+COUNTED_TRAFFIC = {"sources_sha256_prefix": "2e23cceebb1d46c7", "bytes_per_launch": 3159062191.0}
 TRAFFIC_SOURCES = ("fwd_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
+# The same for k_rhs_curv<7,true,true> on the curved workload
+# (profiles/k_rhs_curv_k_face_flux_curv_tgv_n7_32x32x32_curved.md): reads
+# 128 x 46,451,204.6 RDREQ_128B + 64 x 1,941.6 RDREQ_64B, writes 1,310,720 KiB.
+COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "767d9c186cebc8dd", "bytes_per_launch": 7288055731.0}
+TRAFFIC_SOURCES_CURVED = ("curv_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 
 
-def counted_traffic():
+def counted_traffic(counted=COUNTED_TRAFFIC, sources=TRAFFIC_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2606_18927_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest()[:16] != COUNTED_TRAFFIC["sources_sha256_prefix"]:
+    if h.hexdigest()[:16] != counted["sources_sha256_prefix"]:
         return None
-    return COUNTED_TRAFFIC["bytes_per_launch"]
+    return counted["bytes_per_launch"]
 
 
 def _parse():
@@ -153,6 +158,9 @@ def run_curved(steps, warmup):
            "face_kernel_gbs": dof * b["face"] / face_s / 1e9,
            "step_alg_bytes_per_dof": step_bytes / (dof * stages), "step_alg_gbs": step_bytes / (ms / 1e3) / 1e9,
            "step_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+    traffic = counted_traffic(COUNTED_TRAFFIC_CURVED, TRAFFIC_SOURCES_CURVED)
+    out["rk_traffic"] = traffic
+    out["rk_traffic_over_algorithmic"] = None if traffic is None else traffic / rk_bytes
     del S
     torch.cuda.empty_cache()
     return out
