@@ -198,14 +198,20 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
     sq[2][tid] = P.w;
     sq[3][tid] = P.T;
   }
+  // face lanes fetch the neighbour's face node now and take their own values
+  // from LDS after the barrier
+  double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
   if (tid < 6 * NF) {
     const FaceTask<N> ft(tid);
     const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
-    double so[5], sn[5];
-    load_state(U, stride, e * NN + ft.own_node(), so);
     load_state(U, stride, nb * NN + ft.nb_node(), sn);
-    const Prim Po = primitives(so, ph), Pn = primitives(sn, ph);
-    const double qo[4] = {Po.u, Po.v, Po.w, Po.T}, qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
+  }
+  __syncthreads();
+  if (tid < 6 * NF) {
+    const FaceTask<N> ft(tid);
+    const int lo = ft.own_node();
+    const Prim Pn = primitives(sn, ph);
+    const double qo[4] = {sq[0][lo], sq[1][lo], sq[2][lo], sq[3][lo]}, qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
     const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
 #pragma unroll
     for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (0.5 * (qo[c] + qn[c]) - qo[c]) * sc;
