@@ -13,6 +13,22 @@
 
 #include "dg_internal.hpp"
 
+namespace dg {
+
+// Wall faces of the mesh: 2 nb nc per direction with wall ends (host only).
+long long wall_faces(const DevMesh& m) {
+  long long n = 0;
+  for (int d = 0; d < 3; ++d) {
+    if (m.bc[d] == DG_BC_PERIODIC) continue;
+    const int na = d == 0 ? m.n[1] : m.n[0];
+    const int nb = d == 2 ? m.n[1] : m.n[2];
+    n += 2LL * na * nb;
+  }
+  return n;
+}
+
+}  // namespace dg
+
 namespace {
 
 // Carpenter-Kennedy five-stage fourth-order 2N-storage coefficients

@@ -50,7 +50,7 @@ struct Stage {
 
 // Kernel launchers.  ffv (face viscous fluxes, face_flux_values_per_element
 // values per element) is double* for DG_FP64 and float* for DG_MIXED.
-size_t face_flux_values_per_element(int N);
+inline size_t face_flux_values_per_element(int N) { return static_cast<size_t>(6 * 4 * (N + 1) * (N + 1)); }
 hipError_t launch_face_flux(int N, int precision, const DevMesh& m, const DevPhys& p,
                             const DevBasis& b, const double* U, void* ffv, hipStream_t s);
 hipError_t launch_rhs(int N, int precision, const DevMesh& m, const DevPhys& p,

@@ -1106,7 +1106,6 @@ hipError_t rhs_dispatch(int N, const DevMesh& m, const DevPhys& p, const DevBasi
 
 }  // namespace
 
-size_t face_flux_values_per_element(int N) { return static_cast<size_t>(6 * 4 * (N + 1) * (N + 1)); }
 
 hipError_t launch_face_flux(int N, int precision, const DevMesh& m, const DevPhys& p,
                             const DevBasis& b, const double* U, void* ffv, hipStream_t s) {

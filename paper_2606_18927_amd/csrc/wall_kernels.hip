@@ -156,17 +156,6 @@ __global__ __launch_bounds__(256) void k_wall_stress(const double* __restrict__ 
 
 }  // namespace
 
-long long wall_faces(const DevMesh& m) {
-  long long n = 0;
-  for (int d = 0; d < 3; ++d) {
-    if (m.bc[d] == DG_BC_PERIODIC) continue;
-    const int na = d == 0 ? m.n[1] : m.n[0];
-    const int nb = d == 2 ? m.n[1] : m.n[2];
-    n += 2LL * na * nb;
-  }
-  return n;
-}
-
 hipError_t launch_wall_stress(int N, const DevMesh& m, const DevPhys& p, const double* U, int n_wm,
                               double xi_wm1, double recovery, double* tau, hipStream_t s) {
   const long long tasks = wall_faces(m) * (N + 1) * (N + 1);
