@@ -8,7 +8,8 @@ definitions, in the notation of the Cartesian operator (``dgsem``):
 * geometry: element e maps the reference cube [-1, 1]^3 to physical space by
   the degree-N interpolant of its node coordinates X at the LGL nodes
   (isoparametric); the connectivity is that of the structured tensor mesh
-  (neighbours ex +- 1, ey +- 1, ez +- 1), periodic in every direction;
+  (neighbours ex +- 1, ey +- 1, ez +- 1); each direction periodic or closed
+  at both ends by an isothermal no-slip wall;
 * metric terms (reading: Kopriva's conservative curl form, which makes the
   discrete metric identities sum_i d/dxi^i (J a^i_n) = 0 hold and gives both
   elements of a face the same normal):
@@ -22,7 +23,8 @@ definitions, in the notation of the Cartesian operator (``dgsem``):
 * lifting (BR1, strong form; reading: chain rule with the node's own metric):
       J grad q = sum_i J a^i ( sum_m D_im q_m + delta_iN (q*_R - q_N) / w_N
                                             - delta_i0 (q*_L - q_0) / w_0 ),
-  q* the mean of the two sides' primitives at a shared face node;
+  q* the mean of the two sides' primitives at a shared face node, and
+  (0, 0, 0, T_wall) at a wall;
 * right-hand side (strong form):
       J Ut = - sum_i ( 2 sum_m D_im F#^i(U_a, U_m) - sum_m D_im Fv^i_m
                        + delta_iN ((F* - Fv*)_R - (F^i - Fv^i)(U_N)) / w_N
@@ -40,7 +42,11 @@ definitions, in the notation of the Cartesian operator (``dgsem``):
       Lax-Friedrichs
       F* = sum_d f#_d(L, R) s_d - lambda/2 |s| (U_R - U_L),
       lambda = max(|u_L . n| + c_L, |u_R . n| + c_R), n = s / |s|;
-      BR1 central viscous flux Fv* = (Fv^i(L) + Fv^i(R)) / 2.
+      BR1 central viscous flux Fv* = (Fv^i(L) + Fv^i(R)) / 2;
+    - at a wall face, with the own face node's normal s: the pressure-only
+      convective flux (0, p s, 0) and the viscous flux contracted with s for
+      zero velocity and the interior gradients (the Cartesian wall of
+      ``physics`` with e_d replaced by s).
 On an affine box the metric terms are J a^i = J s_i e_i and everything above
 reduces to the Cartesian operator.  ``metric_form = "cross"`` computes
 J a^i = dX/dxi^j x dX/dxi^k directly instead: a negative control whose
@@ -55,8 +61,8 @@ from dataclasses import dataclass
 import torch
 
 from .basis import diff_matrix, lgl
-from .dgsem import _apply_D, _at_node, _prim_line, _prim_plane, _prim_roll, lsrk
-from .mesh import ELEM_AXIS, NODE_AXIS
+from .dgsem import _apply_D, _at_node, _end_mask, _prim_line, _prim_plane, _prim_roll, lsrk
+from .mesh import ELEM_AXIS, NODE_AXIS, PERIODIC, WALL
 from .physics import Gas, euler_flux, kg_flux, primitives, rabs, rmax, viscous_flux
 
 __all__ = ["CurvMesh", "metrics", "lift", "rhs", "rk_step", "llf_flux_metric"]
@@ -67,8 +73,13 @@ class CurvMesh:
     N: int
     X: torch.Tensor          # (3, nz, ny, nx, N+1, N+1, N+1) node coordinates
     metric_form: str = "curl"
+    bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    T_wall: float = 1.0
 
     def __post_init__(self):
+        for b in self.bc:
+            if b not in (PERIODIC, WALL):
+                raise ValueError(f"curved elements take periodic or wall ends, not {b!r}")
         self.X = torch.as_tensor(self.X, dtype=torch.float64)
         if self.X.dim() != 7 or self.X.shape[0] != 3 or any(s != self.N + 1 for s in self.X.shape[4:]):
             raise ValueError("X must be shaped (3, nz, ny, nx, N+1, N+1, N+1)")
@@ -141,6 +152,10 @@ def lift(U: torch.Tensor, mesh: CurvMesh, gas: Gas, geo=None):
             lo, hi = q[c].select(na, 0), q[c].select(na, N)
             star_lo = 0.5 * (lo + torch.roll(hi, 1, ea))
             star_hi = 0.5 * (hi + torch.roll(lo, -1, ea))
+            if mesh.bc[i] == WALL:
+                wv = torch.full_like(lo, (0.0, 0.0, 0.0, mesh.T_wall)[c])
+                star_lo = torch.where(_end_mask(lo, ea, last=False), wv, star_lo)
+                star_hi = torch.where(_end_mask(hi, ea, last=True), wv, star_hi)
             surf = (_at_node(star_hi - hi, na, N, NP) / w[N]
                     - _at_node(star_lo - lo, na, 0, NP) / w[0])
             gxi[c][i] = vol + surf
@@ -209,6 +224,19 @@ def rhs(U: torch.Tensor, mesh: CurvMesh, gas: Gas, *, viscous: bool = True,
         Fv_R = [torch.roll(Fv[v].select(na, 0), -1, ea) for v in range(5)]
         F_hi = [Fs[v] - 0.5 * (Fv_L[v] + Fv_R[v]) for v in range(5)]
         F_lo = [torch.roll(F_hi[v], 1, ea) for v in range(5)]
+        if mesh.bc[i] == WALL:
+            for idx, F, last in ((0, F_lo, False), (N, F_hi, True)):
+                Pw = _prim_plane(P, na, idx)
+                sw = [Jai[d].select(na, idx) for d in range(3)]
+                zero = torch.zeros_like(Pw.p)
+                fw = [zero] + [Pw.p * sw[a] for a in range(3)] + [zero]
+                if viscous:
+                    g_plane = [[grad[c][b].select(na, idx) for b in range(3)] for c in range(4)]
+                    fvw = [viscous_flux((zero, zero, zero), g_plane, d, gas, Pw.T) for d in range(3)]
+                    fw = [fw[v] - sum(fvw[d][v] * sw[d] for d in range(3)) for v in range(5)]
+                mask = _end_mask(Pw.p, ea, last)
+                for v in range(5):
+                    F[v] = torch.where(mask, fw[v], F[v])
         for v in range(5):
             surf = (_at_node(F_hi[v] - own_hi[v], na, N, NP) / w[N]
                     - _at_node(F_lo[v] - own_lo[v], na, 0, NP) / w[0])

@@ -39,7 +39,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-__all__ = ["Workload", "WORKLOADS", "tgv_faces", "channel_faces", "node_coords", "warped_nodes",
+__all__ = ["Workload", "WORKLOADS", "tgv_faces", "channel_faces", "node_coords", "warped_nodes", "wavy_channel_nodes",
            "make_state", "cfl_dt", "fd_direction"]
 
 TGV_SEED = 20260001
@@ -201,6 +201,31 @@ def warped_nodes(xi, nelem, lengths=(2.0 * np.pi,) * 3, amp=0.05):
     Lx, Ly, Lz = lengths
     sx, sy, sz = np.sin(2 * np.pi * X / Lx), np.sin(2 * np.pi * Y / Ly), np.sin(2 * np.pi * Z / Lz)
     return np.stack([X + amp * Lx * sy * sz, Y + amp * Ly * sx * sz, Z + amp * Lz * sx * sy])
+
+
+def wavy_channel_nodes(xi, nelem, lengths=(2.0 * np.pi, 2.0, np.pi), amp=0.05):
+    """Node coordinates (3, nz, ny, nx, NP, NP, NP) of a channel with wavy walls:
+    the uniform tensor mesh of [0, L_x] x [-L_y/2, L_y/2] x [0, L_z] (nodes
+    exact at the element ends), each node displaced by
+      dx = amp L_x sin(2 pi z / L_z) cos(pi y / L_y),
+      dy = amp L_y sin(2 pi x / L_x) sin(2 pi z / L_z) / 2,
+      dz = amp L_z sin(2 pi x / L_x) cos(pi y / L_y),
+    at its undisplaced position: periodic in x and z, walls y = +-L_y/2 + dy."""
+    xi = np.asarray(xi, dtype=np.float64)
+    NP = xi.size
+    lo = (0.0, -lengths[1] / 2.0, 0.0)
+    tabs = []
+    for n, L, a in zip(nelem, lengths, lo):
+        f = a + L * np.arange(n + 1, dtype=np.float64) / n
+        tabs.append(f[:-1, None] * (1.0 - xi[None, :]) / 2.0 + f[1:, None] * (1.0 + xi[None, :]) / 2.0)
+    nx, ny, nz = nelem
+    shape = (nz, ny, nx, NP, NP, NP)
+    X = np.broadcast_to(tabs[0].reshape(1, 1, nx, 1, 1, NP), shape)
+    Y = np.broadcast_to(tabs[1].reshape(1, ny, 1, 1, NP, 1), shape)
+    Z = np.broadcast_to(tabs[2].reshape(nz, 1, 1, NP, 1, 1), shape)
+    Lx, Ly, Lz = lengths
+    sx, sz, cy = np.sin(2 * np.pi * X / Lx), np.sin(2 * np.pi * Z / Lz), np.cos(np.pi * Y / Ly)
+    return np.stack([X + amp * Lx * sz * cy, Y + amp * Ly * sx * sz / 2.0, Z + amp * Lz * sx * cy])
 
 
 def _widths(faces):
