@@ -96,10 +96,11 @@ typedef struct {
                          each element is the degree-N interpolant of its nodes
                          (Kopriva's curl-form metric terms, contravariant
                          two-point fluxes with averaged metrics); the elements
-                         keep the structured connectivity of nelem, all ends
-                         periodic; faces may be NULL.  DG_FP64, DG_FLUX_KG_LLF
-                         only; no adjoint, lifting or kinetic-energy calls
-                         (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
+                         keep the structured connectivity of nelem, periodic
+                         or isothermal-wall ends (the wall normal is the face's
+                         metric vector); faces may be NULL.  DG_FP64,
+                         DG_FLUX_KG_LLF only; no wall model, adjoint, lifting
+                         or kinetic-energy calls (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
                          makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;
 

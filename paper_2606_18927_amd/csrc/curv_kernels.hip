@@ -1,4 +1,5 @@
-// Split-form DGSEM on curvilinear hexahedra (FP64, periodic structured meshes).
+// Split-form DGSEM on curvilinear hexahedra (FP64, structured meshes with
+// periodic or isothermal no-slip wall ends).
 //
 // Geometry (the paper's production meshes are curved, Sec. 4): each element's
 // map is the degree-N interpolant of its node coordinates.  The metric terms
@@ -201,20 +202,28 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
   // face lanes fetch the neighbour's face node now and take their own values
   // from LDS after the barrier
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  long long nb = -1;  // -1: the face is a wall
   if (tid < 6 * NF) {
     const FaceTask<N> ft(tid);
-    const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
-    load_state(U, stride, nb * NN + ft.nb_node(), sn);
+    nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
+    if (nb >= 0) load_state(U, stride, nb * NN + ft.nb_node(), sn);
   }
   __syncthreads();
   if (tid < 6 * NF) {
     const FaceTask<N> ft(tid);
     const int lo = ft.own_node();
-    const Prim Pn = primitives(sn, ph);
-    const double qo[4] = {sq[0][lo], sq[1][lo], sq[2][lo], sq[3][lo]}, qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
+    const double qo[4] = {sq[0][lo], sq[1][lo], sq[2][lo], sq[3][lo]};
+    double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};  // isothermal no-slip wall
+    if (nb >= 0) {
+      const Prim Pn = primitives(sn, ph);
+      qs[0] = 0.5 * (qo[0] + Pn.u);
+      qs[1] = 0.5 * (qo[1] + Pn.v);
+      qs[2] = 0.5 * (qo[2] + Pn.w);
+      qs[3] = 0.5 * (qo[3] + Pn.T);
+    }
     const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (0.5 * (qo[c] + qn[c]) - qo[c]) * sc;
+    for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (qs[c] - qo[c]) * sc;
   }
   __syncthreads();
   if (tid >= NN) return;
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   // P1: own state; face lanes fetch the neighbour's face node (registers are
   // the limit of this kernel: metric terms, the neighbour's state and the own
   // primitives are fetched again where they are used, from L2 and LDS)
-  long long nb = 0;
+  long long nb = -1;  // -1: the face is a wall
   if (face_lane) {
     const FaceTask<N> ft(tid);
     nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
@@ -297,7 +306,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     if (VISC) sT[tid] = P.T;
   }
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-  if (VISC && face_lane) load_state(U, stride, nb * NN + FaceTask<N>(tid).nb_node(), sn);
+  if (VISC && face_lane && nb >= 0) load_state(U, stride, nb * NN + FaceTask<N>(tid).nb_node(), sn);
   __syncthreads();
 
   // P1b: BR1 lifting terms of the face nodes
@@ -306,11 +315,17 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       const FaceTask<N> ft(tid);
       const int lo = ft.own_node();
       const double qo[4] = {sp[1][lo], sp[2][lo], sp[3][lo], sT[lo]};
-      const Prim Pn = primitives(sn, ph);
-      const double qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
+      double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};  // isothermal no-slip wall
+      if (nb >= 0) {
+        const Prim Pn = primitives(sn, ph);
+        qs[0] = 0.5 * (qo[0] + Pn.u);
+        qs[1] = 0.5 * (qo[1] + Pn.v);
+        qs[2] = 0.5 * (qo[2] + Pn.w);
+        qs[3] = 0.5 * (qo[3] + Pn.T);
+      }
       const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (0.5 * (qo[c] + qn[c]) - qo[c]) * sc;
+      for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (qs[c] - qo[c]) * sc;
     }
     __syncthreads();
   }
@@ -403,12 +418,14 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     // the neighbour's on a lower face), so the two sides' fluxes are exact
     // negatives even where the face nodes of the two elements differ in
     // rounding (the periodic seam)
+    // (a wall face has no element on its other side: the own normal)
+    const bool fwall = nb < 0;
     double s[3];
-    const long long gi = ft.up ? e * NN + lo : nb * NN + ft.nb_node();
+    const long long gi = (ft.up || fwall) ? e * NN + lo : nb * NN + ft.nb_node();
 #pragma unroll
     for (int c = 0; c < 3; ++c) s[c] = mesh.geo[(3 * ft.d + c) * stride + gi];
     const double Ao[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
-    load_state(U, stride, nb * NN + ft.nb_node(), sn);
+    if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
     const Prim Pn = primitives(sn, ph);
     const double An[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
     const double so[5] = {Ao[0], Ao[0] * Ao[1], Ao[0] * Ao[2], Ao[0] * Ao[3], Ao[0] * Ao[5]};
@@ -423,7 +440,13 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     const double mass = rho * Uc;
     double Fs[5] = {mass, mass * uu + pp * s[0], mass * vv + pp * s[1], mass * ww + pp * s[2],
                     mass * ee + pp * Uc};
-    if (!ph.central) {
+    if (fwall) {  // impermeable wall: the interior pressure only
+      Fs[0] = 0.0;
+      Fs[1] = Ao[4] * s[0];
+      Fs[2] = Ao[4] * s[1];
+      Fs[3] = Ao[4] * s[2];
+      Fs[4] = 0.0;
+    } else if (!ph.central) {
       const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
       const double co = sqrt(ph.gamma * Ao[4] / Ao[0]), cn = sqrt(ph.gamma * An[4] / An[0]);
       const double uno = Uo / smag, unn = (An[1] * s[0] + An[2] * s[1] + An[3] * s[2]) / smag;
@@ -437,11 +460,18 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     }
     double fvo[4] = {0, 0, 0, 0}, fvs[4] = {0, 0, 0, 0};
     if (VISC) {
-      const double* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        fvo[c] = sX[ft.f][c][ft.ab];
-        fvs[c] = 0.5 * (fvo[c] + src[c * NF]);
+      for (int c = 0; c < 4; ++c) fvo[c] = sX[ft.f][c][ft.ab];
+      if (fwall) {
+        // zero wall velocity with the interior gradients: the own stresses,
+        // and of the energy flux only the heat flux
+#pragma unroll
+        for (int c = 0; c < 3; ++c) fvs[c] = fvo[c];
+        fvs[3] = fvo[3] - (Ao[1] * fvo[0] + Ao[2] * fvo[1] + Ao[3] * fvo[2]);
+      } else {
+        const double* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) fvs[c] = 0.5 * (fvo[c] + src[c * NF]);
       }
     }
     const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;

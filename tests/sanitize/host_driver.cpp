@@ -124,6 +124,10 @@ int main() {
     EXPECT(dg_init_mesh(&m.d, &p, nullptr, &c) == DG_EINVAL && c == nullptr);
     X[3 * ndof - 1] = 0.0;
     m.d.bc[1] = DG_BC_ISOTHERMAL_WALL;
+    c = nullptr;
+    EXPECT(dg_init_mesh(&m.d, &p, nullptr, &c) == DG_OK);
+    if (c) dg_free(c);
+    m.d.bc[1] = DG_BC_WALL_MODEL;
     EXPECT(dg_init_mesh(&m.d, &p, nullptr, &c) == DG_EUNSUPPORTED);
   }
   // invalid arguments

@@ -161,8 +161,9 @@ def test_wall_face_count(L):
 
 
 def test_curved_mesh_validation(L):
-    """Curved elements (node coordinates given): periodic, FP64, Kennedy-Gruber
-    only; faces may be absent; non-finite coordinates are rejected.  Host only."""
+    """Curved elements (node coordinates given): periodic or isothermal-wall
+    ends, FP64, Kennedy-Gruber only; faces may be absent; non-finite
+    coordinates are rejected.  Host only."""
     from paper_2606_18927_amd.workloads import warped_nodes
     N, n = 3, (2, 2, 2)
     X = np.ascontiguousarray(warped_nodes(dgsem.lgl(N)[0], n)).reshape(-1)
@@ -191,7 +192,12 @@ def test_curved_mesh_validation(L):
     for bad, code in ((dict(precision=1), dgsem.DG_EUNSUPPORTED), (dict(flux=1), dgsem.DG_EUNSUPPORTED)):
         d, keep = desc()
         assert _init(L, d, _phys(**bad))[0] == code, bad
-    d, keep = desc(bc=(0, 1, 0))
+    d, keep = desc(bc=(0, 1, 0))  # isothermal walls are fine
+    st, ctx = _init(L, d, _phys())
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
+    d, keep = desc(bc=(0, 2, 0))  # the wall model is not
+    d.wm_node = 1
     assert _init(L, d, _phys())[0] == dgsem.DG_EUNSUPPORTED
     Xn = X.copy()
     Xn[17] = np.nan

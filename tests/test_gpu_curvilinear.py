@@ -28,8 +28,8 @@ TOL = 1e-12
 GAS = Gas(gamma=1.4, R=1.0, mu=0.02, Pr=0.72)
 
 
-def _solver(N, X, g, **kw):
-    spec = dgsem.MeshSpec(N, None, nodes=X)
+def _solver(N, X, g, bc=("periodic",) * 3, T_wall=1.0, **kw):
+    spec = dgsem.MeshSpec(N, None, bc, T_wall, nodes=X)
     suth = (g.T_ref, g.S) if g.sutherland else None
     return dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, sutherland=suth, **kw)
 
@@ -124,6 +124,63 @@ def test_curved_rk_steps():
     e, e2 = _rel_l2_momentum(got, ref), _rel_l2_momentum(got - U, ref - U)
     say("curved TGV N=3, 10 steps: rel L2", e, "increment", e2)
     assert np.all(e < TOL) and np.all(e2 < 1e-9)
+
+
+# ------------------------------------------------- wavy-walled channels
+
+@pytest.mark.parametrize("N,n,viscous,suth", [
+    (3, (2, 3, 2), True, False),
+    (5, (2, 2, 2), True, False),
+    (3, (3, 2, 2), False, False),
+    (5, (2, 3, 2), True, True),
+])
+def test_wavy_channel_rhs_against_oracle(N, n, viscous, suth):
+    need_gpu()
+    say("wavy channel rhs", N, n, viscous, suth)
+    X = workloads.wavy_channel_nodes(dgsem.lgl(N)[0], n, amp=0.06)
+    bc = ("periodic", "wall", "periodic")
+    mesh = cv.CurvMesh(N, torch.as_tensor(X), bc=bc, T_wall=1.3)
+    g = Gas(gamma=1.4, R=1.0, mu=0.02, Pr=0.72, sutherland=True, T_ref=1.0, S=0.4) if suth else GAS
+    U = random_state(mesh, g.gamma, g.R, np.random.default_rng(60 + N)).numpy()
+    S = _solver(N, X, g, bc=bc, T_wall=1.3, viscous=viscous)
+    got = S.eval_rhs(to_dev(U)).cpu().numpy()
+    S.sync()
+    ref = cv.rhs(torch.as_tensor(U), mesh, g, viscous=viscous).numpy()
+    e = rel_l2(got, ref)
+    say("  rel L2", e)
+    assert np.all(e < TOL)
+
+
+def test_wavy_channel_rk_steps_and_rest_state():
+    """Five RK steps of a Poiseuille-like flow between wavy walls against the
+    oracle; fluid at rest at the wall temperature stays at rest."""
+    need_gpu()
+    N, n = 3, (3, 3, 2)
+    X = workloads.wavy_channel_nodes(dgsem.lgl(N)[0], n, amp=0.06)
+    bc = ("periodic", "wall", "periodic")
+    g = Gas(gamma=1.4, R=1.0 / (1.4 * 0.01), mu=1e-2, Pr=0.72)
+    mesh = cv.CurvMesh(N, torch.as_tensor(X), bc=bc, T_wall=1.0)
+    Y = X[1]
+    u = 1.2 * np.clip(1.0 - Y * Y, 0.0, None)
+    rho = np.ones_like(u)
+    p = g.R * rho
+    E = p / 0.4 + 0.5 * rho * u * u
+    z = np.zeros_like(u)
+    U = np.stack([rho, rho * u, z, z, E])
+    S = _solver(N, X, g, bc=bc, T_wall=1.0)
+    dt, nsteps = 2e-4, 5
+    S.set_state(to_dev(U))
+    S.rk_step(dt, nsteps)
+    S.sync()
+    got = S.get_state().cpu().numpy().reshape(U.shape)
+    ref = cv.rk_step(torch.as_tensor(U), mesh, g, dt, nsteps).numpy()
+    e, e2 = _rel_l2_momentum(got, ref), _rel_l2_momentum(got - U, ref - U)
+    say("wavy channel 5 steps rel L2", e, "increment", e2)
+    assert np.all(e < TOL) and np.all(e2 < 1e-9)
+    rest = np.stack([rho, z, z, z, E - 0.5 * rho * u * u])
+    out = S.eval_rhs(to_dev(rest)).cpu().numpy()
+    S.sync()
+    assert np.abs(out).max() < 1e-12 * g.R * 2 * N * N
 
 
 # ------------------------------------------- full N=7, 32^3 curved workload
@@ -244,7 +301,7 @@ def test_curved_rejected_combinations():
         with pytest.raises(dgsem.DgsemError) as ei:
             _solver(N, X, GAS, **kw)
         assert ei.value.status == dgsem.DG_EUNSUPPORTED
-    spec = dgsem.MeshSpec(N, None, ("periodic", "wall", "periodic"), nodes=X)
+    spec = dgsem.MeshSpec(N, None, ("periodic", "wallmodel", "periodic"), nodes=X)
     with pytest.raises(dgsem.DgsemError) as ei:
         dgsem.Solver(spec, 1.4, 1.0, 0.02, 0.72)
     assert ei.value.status == dgsem.DG_EUNSUPPORTED
