@@ -47,6 +47,15 @@ definitions, in the notation of the Cartesian operator (``dgsem``):
       convective flux (0, p s, 0) and the viscous flux contracted with s for
       zero velocity and the interior gradients (the Cartesian wall of
       ``physics`` with e_d replaced by s).
+With ``flux = "ec_roe"`` (the paper's production pair, Sec. 4) the volume flux
+is Chandrashekar's flux contracted with the averaged metric terms,
+sum_d f#EC_d(A, B) (J a^i_d(A) + J a^i_d(B)) / 2, and the surface flux is
+Roe's flux across the face normal n = s / |s| scaled by |s|:
+F* = sum_d f#EC_d(L, R) s_d - |s| / 2 sum_k |lambda_k| alpha_k r_k, with the
+waves of Roe's linearisation along n (acoustic u~.n -+ a~, entropy and shear
+u~.n, the shear jump being the tangential part [[u]] - ([[u]].n) n) and the
+Harten-Hyman correction of the acoustic waves; walls keep the pressure-only
+flux.
 On an affine box the metric terms are J a^i = J s_i e_i and everything above
 reduces to the Cartesian operator.  ``metric_form = "cross"`` computes
 J a^i = dX/dxi^j x dX/dxi^k directly instead: a negative control whose
@@ -63,9 +72,11 @@ import torch
 from .basis import diff_matrix, lgl
 from .dgsem import _apply_D, _at_node, _end_mask, _prim_line, _prim_plane, _prim_roll, lsrk
 from .mesh import ELEM_AXIS, NODE_AXIS, PERIODIC, WALL
-from .physics import Gas, euler_flux, kg_flux, primitives, rabs, rmax, viscous_flux
+from .physics import (FLUXES, Gas, ec_flux, euler_flux, harten_hyman_abs, kg_flux, primitives, rabs, rmax,
+                      viscous_flux)
 
-__all__ = ["CurvMesh", "metrics", "lift", "rhs", "rk_step", "llf_flux_metric"]
+__all__ = ["CurvMesh", "metrics", "lift", "rhs", "rk_step", "llf_flux_metric", "roe_waves_normal",
+           "roe_flux_metric"]
 
 
 @dataclass
@@ -178,9 +189,61 @@ def llf_flux_metric(L, R, UL, UR, s, gas: Gas, central_only: bool = False):
     return [f[v] - 0.5 * lam * smag * (UR[v] - UL[v]) for v in range(5)]
 
 
+def roe_waves_normal(L, R, n, gas: Gas):
+    """Roe's wave decomposition across a face with unit normal n (L on the side
+    n points away from): (lambda, alpha, r) lists with
+    U_R - U_L = sum_k alpha_k r_k.  Shear waves are one entry with alpha = 1
+    and r = rho~ (0, [[u_t]], u~ . [[u_t]]), [[u_t]] = [[u]] - ([[u]] . n) n."""
+    g = gas.gamma
+    sl, sr = torch.sqrt(L.rho), torch.sqrt(R.rho)
+    wl, wr = sl / (sl + sr), sr / (sl + sr)
+    u = [wl * L.vel[c] + wr * R.vel[c] for c in range(3)]
+    H = wl * (L.E + L.p) / L.rho + wr * (R.E + R.p) / R.rho
+    q2 = sum(u[c] * u[c] for c in range(3))
+    a2 = (g - 1.0) * (H - 0.5 * q2)
+    a = torch.sqrt(a2)
+    rho = sl * sr
+    un = sum(u[c] * n[c] for c in range(3))
+    drho = R.rho - L.rho
+    dp = R.p - L.p
+    du = [R.vel[c] - L.vel[c] for c in range(3)]
+    dun = sum(du[c] * n[c] for c in range(3))
+    dut = [du[c] - dun * n[c] for c in range(3)]
+    one = torch.ones_like(a)
+    zero = torch.zeros_like(a)
+    lam = [un - a, un, un, un + a]
+    alpha = [(dp - rho * a * dun) / (2.0 * a2), drho - dp / a2, one, (dp + rho * a * dun) / (2.0 * a2)]
+    r = [[one] + [u[c] - a * n[c] for c in range(3)] + [H - un * a],
+         [one] + u + [0.5 * q2],
+         [zero] + [rho * dut[c] for c in range(3)] + [rho * sum(u[c] * dut[c] for c in range(3))],
+         [one] + [u[c] + a * n[c] for c in range(3)] + [H + un * a]]
+    return lam, alpha, r
+
+
+def roe_flux_metric(L, R, s, gas: Gas, central_only: bool = False):
+    """Roe's flux with the Harten-Hyman correction across a face with normal
+    vector s (not unit): sum_d f#EC_d(L, R) s_d - |s|/2 sum_k |lambda_k| alpha_k r_k."""
+    f = [sum(ec_flux(L, R, d, gas)[v] * s[d] for d in range(3)) for v in range(5)]
+    if central_only:
+        return f
+    smag = torch.sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2])
+    n = [s[c] / smag for c in range(3)]
+    lam, alpha, r = roe_waves_normal(L, R, n, gas)
+    absl = [torch.abs(x) for x in lam]
+    unL = sum(L.vel[c] * n[c] for c in range(3))
+    unR = sum(R.vel[c] * n[c] for c in range(3))
+    cL, cR = L.c(gas), R.c(gas)
+    absl[0] = harten_hyman_abs(lam[0], unL - cL, unR - cR)
+    absl[3] = harten_hyman_abs(lam[3], unL + cL, unR + cR)
+    return [f[v] - 0.5 * smag * sum(absl[k] * alpha[k] * r[k][v] for k in range(4)) for v in range(5)]
+
+
 def rhs(U: torch.Tensor, mesh: CurvMesh, gas: Gas, *, viscous: bool = True,
-        central_only: bool = False, source=None) -> torch.Tensor:
+        central_only: bool = False, source=None, flux: str = "kg_llf") -> torch.Tensor:
     """L(U) of the curvilinear split-form DGSEM (module docstring)."""
+    if flux not in FLUXES:
+        raise ValueError(f"flux must be one of {FLUXES}")
+    ec = flux == "ec_roe"
     N, NP = mesh.N, mesh.NP
     D = diff_matrix(N).to(U.dtype)
     _, w = lgl(N)
@@ -198,7 +261,7 @@ def rhs(U: torch.Tensor, mesh: CurvMesh, gas: Gas, *, viscous: bool = True,
         Pa, Pm = _prim_line(P, na, -2), _prim_line(P, na, -1)
         Ma = [Jai[d].movedim(na, -1).unsqueeze(-1) for d in range(3)]
         Mm = [Jai[d].movedim(na, -1).unsqueeze(-2) for d in range(3)]
-        fsharp = [kg_flux(Pa, Pm, d) for d in range(3)]
+        fsharp = [ec_flux(Pa, Pm, d, gas) if ec else kg_flux(Pa, Pm, d) for d in range(3)]
         F2 = [sum(fsharp[d][v] * (0.5 * (Ma[d] + Mm[d])) for d in range(3)) for v in range(5)]
         vol_c = [(2.0 * (D * F2[v]).sum(-1)).movedim(-1, na) for v in range(5)]
 
@@ -219,7 +282,8 @@ def rhs(U: torch.Tensor, mesh: CurvMesh, gas: Gas, *, viscous: bool = True,
         P_R = _prim_roll(_prim_plane(P, na, 0), -1, ea)
         U_hi = [U[v].select(na, N) for v in range(5)]
         U_R = [torch.roll(U[v].select(na, 0), -1, ea) for v in range(5)]
-        Fs = llf_flux_metric(P_hi, P_R, U_hi, U_R, s, gas, central_only)
+        Fs = roe_flux_metric(P_hi, P_R, s, gas, central_only) if ec else \
+            llf_flux_metric(P_hi, P_R, U_hi, U_R, s, gas, central_only)
         Fv_L = [Fv[v].select(na, N) for v in range(5)]
         Fv_R = [torch.roll(Fv[v].select(na, 0), -1, ea) for v in range(5)]
         F_hi = [Fs[v] - 0.5 * (Fv_L[v] + Fv_R[v]) for v in range(5)]

@@ -19,7 +19,13 @@
   Cartesian operator with walls (itself pinned by the exact discrete
   Poiseuille state); fluid at rest at the wall temperature between wavy
   walls has Ut = 0 to rounding (and is disturbed by another wall
-  temperature); mass is conserved between wavy walls.
+  temperature); mass is conserved between wavy walls;
+* the entropy-conserving / Roe pair on curved elements: the Roe flux along a
+  normal vector equals the pinned axis-aligned Roe flux for axis normals and
+  is rotation invariant; an affine box reproduces the Cartesian operator;
+  the Euler central form conserves the total entropy on warped meshes
+  (Kennedy-Gruber does not; Roe dissipation makes the rate negative); free
+  streams are preserved.
 """
 
 import math
@@ -214,3 +220,97 @@ def test_mass_conservation_between_wavy_walls():
     assert abs(tot) < 1e-13 * mag
     # energy is not conserved (the walls conduct heat), momentum feels the wall pressure
     assert abs((wq * out[4]).sum().item()) > 1e-8 * (wq * out[4].abs()).sum().item()
+
+
+# ------------------------------------- entropy-conserving / Roe pair
+
+def _random_prims(rng, shape=(7,)):
+    from oracle.physics import primitives
+    rho = 1.0 + 0.3 * rng.uniform(-1, 1, shape)
+    vel = 0.6 * rng.uniform(-1, 1, (3,) + shape)
+    p = 1.0 + 0.3 * rng.uniform(-1, 1, shape)
+    E = p / 0.4 + 0.5 * rho * (vel ** 2).sum(0)
+    U = torch.as_tensor(np.stack([rho, rho * vel[0], rho * vel[1], rho * vel[2], E]))
+    return primitives(U, GAS), U
+
+
+def test_roe_flux_metric_axis_normals_match_axis_flux():
+    from oracle.physics import roe_flux
+    rng = np.random.default_rng(21)
+    L, _ = _random_prims(rng)
+    R, _ = _random_prims(rng)
+    for d in range(3):
+        for sig in (0.37, 2.5):
+            s = [torch.full((7,), sig if c == d else 0.0, dtype=torch.float64) for c in range(3)]
+            got = cv.roe_flux_metric(L, R, s, GAS)
+            ref = roe_flux(L, R, d, GAS)
+            for v in range(5):
+                assert torch.allclose(got[v], sig * ref[v], rtol=1e-14, atol=1e-14)
+
+
+def test_roe_flux_metric_rotation_invariance():
+    from oracle.physics import Prim
+    rng = np.random.default_rng(22)
+    L, _ = _random_prims(rng)
+    R, _ = _random_prims(rng)
+    s = [torch.as_tensor(rng.uniform(-1, 1, 7)) for _ in range(3)]
+    a = np.array([2.0, -1.0, 2.0]) / 3.0
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    Q = np.eye(3) + math.sin(1.1) * K + (1 - math.cos(1.1)) * K @ K
+    rot = lambda v: [sum(Q[i, j] * v[j] for j in range(3)) for i in range(3)]  # noqa: E731
+    Lr = Prim(L.rho, tuple(rot(L.vel)), L.p, L.T, L.e, L.E)
+    Rr = Prim(R.rho, tuple(rot(R.vel)), R.p, R.T, R.e, R.E)
+    f = cv.roe_flux_metric(L, R, s, GAS)
+    fr = cv.roe_flux_metric(Lr, Rr, rot(s), GAS)
+    for v, ref in ((0, f[0]), (4, f[4])):
+        assert torch.allclose(fr[v], ref, rtol=1e-13, atol=1e-13)
+    mom = rot(f[1:4])
+    for c in range(3):
+        assert torch.allclose(fr[1 + c], mom[c], rtol=1e-13, atol=1e-13)
+
+
+@pytest.mark.parametrize("viscous", [True, False])
+def test_ec_reduces_to_cartesian_operator(viscous):
+    rng = np.random.default_rng(23)
+    box = Mesh(3, tuple(random_faces(n, 0.0, TWO_PI, rng) for n in (2, 3, 2)))
+    U = random_state(box, GAS.gamma, GAS.R, rng)
+    ref = rhs_cart(U, box, GAS, viscous=viscous, flux="ec_roe")
+    got = cv.rhs(U, cv.CurvMesh(3, _box_nodes(box)), GAS, viscous=viscous, flux="ec_roe")
+    for v in range(5):
+        assert torch.linalg.norm(got[v] - ref[v]) <= 1e-13 * torch.linalg.norm(ref[v])
+
+
+def _entropy_rate(U, mesh, out):
+    from oracle.physics import entropy_variables, primitives
+    v = entropy_variables(primitives(U, GAS), GAS)
+    wq = mesh.quadrature_weights()
+    terms = sum(wq * v[k] * out[k] for k in range(5))
+    return terms.sum().item(), terms.abs().sum().item()
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_ec_entropy_conservation_on_warped_mesh(N):
+    """Euler, central surface flux: the curvilinear entropy-conserving split
+    form conserves the total entropy semi-discretely (metric identities plus
+    Tadmor's condition); the Kennedy-Gruber form does not; the Roe
+    dissipation makes the entropy rate negative."""
+    rng = np.random.default_rng(24 + N)
+    mesh = _warped(N, (2, 2, 3), amp=0.08)
+    U = random_state(mesh, GAS.gamma, GAS.R, rng)
+    tot, mag = _entropy_rate(U, mesh, cv.rhs(U, mesh, GAS, viscous=False, central_only=True, flux="ec_roe"))
+    assert abs(tot) < 1e-12 * mag
+    tot_kg, mag_kg = _entropy_rate(U, mesh, cv.rhs(U, mesh, GAS, viscous=False, central_only=True))
+    assert abs(tot_kg) > 1e-6 * mag_kg
+    tot_roe, mag_roe = _entropy_rate(U, mesh, cv.rhs(U, mesh, GAS, viscous=False, flux="ec_roe"))
+    assert tot_roe < -1e-6 * mag_roe
+
+
+def test_ec_free_stream_preservation_warped():
+    N = 5
+    mesh = _warped(N, (2, 2, 3), amp=0.08)
+    shape = mesh.shape
+    rho, u, v, w, p = 1.3, 0.4, -0.25, 0.15, 2.0
+    E = p / (GAS.gamma - 1) + 0.5 * rho * (u * u + v * v + w * w)
+    U = torch.stack([torch.full(shape, x, dtype=torch.float64) for x in (rho, rho * u, rho * v, rho * w, E)])
+    out = cv.rhs(U, mesh, GAS, flux="ec_roe")
+    assert out.abs().max().item() < 1e-12 * (abs(rho * u) + p + E) * 2 * N * N
