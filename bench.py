@@ -133,15 +133,16 @@ def curved_alg_bytes(N: int = 7):
             "rk_first": 40 + ff + 80 + 80}
 
 
-def run_curved(steps, warmup):
-    """The Taylor-Green step on the warped (curved) N = 7, 32^3 mesh, FP64."""
+def run_curved(steps, warmup, flux=None):
+    """The Taylor-Green step on the warped (curved) N = 7, 32^3 mesh, FP64
+    (the workload's Kennedy-Gruber / Lax-Friedrichs pair unless `flux`)."""
     import torch
 
     from paper_2606_18927_amd import dgsem, workloads
     wl = workloads.WORKLOADS["tgv_n7_32x32x32_curved"]
     xi, _ = dgsem.lgl(wl.N)
     U, dt = workloads.make_state(wl, xi)
-    S = dgsem.solver_for(wl)
+    S = dgsem.solver_for(wl, flux=flux)
     S.set_state(torch.as_tensor(U.reshape(-1)).cuda())
     del U
     ms, lift_ms, rk_ms, n_lift, n_rk = time_steps(S, dt, steps, warmup)
@@ -151,14 +152,15 @@ def run_curved(steps, warmup):
     rk_s = rk_ms / 1e3 / n_rk
     face_s = lift_ms / 1e3 / max(n_lift, 1)
     step_bytes = dof * (b["face"] * stages + b["rk"] * (stages - steps) + b["rk_first"] * steps)
-    out = {"workload": wl.name, "warp": wl.warp, "ns_per_dof_stage": ms * 1e6 / (dof * stages),
+    out = {"workload": wl.name, "warp": wl.warp, "flux": flux or wl.flux,
+           "ns_per_dof_stage": ms * 1e6 / (dof * stages),
            "ms_per_step": ms / steps, "rk_kernel": "k_rhs_curv", "rk_kernel_ms": rk_ms / n_rk,
            "face_kernel_ms": lift_ms / max(n_lift, 1), "rk_bytes_per_launch": rk_bytes,
            "rk_kernel_gbs": rk_bytes / rk_s / 1e9, "rk_frac": rk_bytes / rk_s / 1e9 / HBM_PEAK_GBS,
            "face_kernel_gbs": dof * b["face"] / face_s / 1e9,
            "step_alg_bytes_per_dof": step_bytes / (dof * stages), "step_alg_gbs": step_bytes / (ms / 1e3) / 1e9,
            "step_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
-    traffic = counted_traffic(COUNTED_TRAFFIC_CURVED, TRAFFIC_SOURCES_CURVED)
+    traffic = counted_traffic(COUNTED_TRAFFIC_CURVED, TRAFFIC_SOURCES_CURVED) if flux is None else None
     out["rk_traffic"] = traffic
     out["rk_traffic_over_algorithmic"] = None if traffic is None else traffic / rk_bytes
     del S
@@ -419,6 +421,11 @@ def main():
             curved = run_curved(args.steps, args.warmup)
             print(f"[bench] curved {curved['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage, k_rhs_curv "
                   f"{curved['rk_kernel_ms']*1e3:.0f} us ({curved['rk_frac']*100:.0f} % of HBM)", file=sys.stderr,
+                  flush=True)
+            cec = run_curved(args.steps, args.warmup, flux="ec_roe")
+            curved["ec_roe"] = {k: cec[k] for k in ("ns_per_dof_stage", "ms_per_step", "rk_kernel_ms",
+                                                     "face_kernel_ms", "step_frac")}
+            print(f"[bench] curved ec_roe {cec['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
                   flush=True)
         except dgsem.DgsemError as e:
             curved = {"error": str(e)}

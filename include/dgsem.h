@@ -98,9 +98,10 @@ typedef struct {
                          two-point fluxes with averaged metrics); the elements
                          keep the structured connectivity of nelem, periodic
                          or isothermal-wall ends (the wall normal is the face's
-                         metric vector); faces may be NULL.  DG_FP64,
-                         DG_FLUX_KG_LLF only; no wall model, adjoint, lifting
-                         or kinetic-energy calls (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
+                         metric vector); faces may be NULL.  DG_FP64 with either
+                         flux pair (the Roe flux along the face's unit normal,
+                         scaled by its length); no wall model, adjoint,
+                         lifting or kinetic-energy calls (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
                          makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;
 

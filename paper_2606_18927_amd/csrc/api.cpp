@@ -331,7 +331,7 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;
   }
   if (curved) {
-    if (wall_model || phys->precision != DG_FP64 || phys->flux != DG_FLUX_KG_LLF) return DG_EUNSUPPORTED;
+    if (wall_model || phys->precision != DG_FP64) return DG_EUNSUPPORTED;
     const long long n3 = 3 * nE * nn;
     for (long long q = 0; q < n3; ++q)
       if (!std::isfinite(mesh->nodes[q])) return DG_EINVAL;

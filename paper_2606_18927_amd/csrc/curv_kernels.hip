@@ -49,6 +49,72 @@ __device__ inline double dline(const double* f, const double (*sD)[N + 2], int d
   return a;
 }
 
+// Chandrashekar's flux contracted with the metric vector M (the average of the
+// two nodes' J a^i in the volume, the face normal on a face): with
+// a, b = (rho, u, v, w, beta, |u|^2), beta = rho / (2 p), U~ = {{u}} . M,
+//   F_rho = rho_ln U~,  F_m = F_rho {{u}} + p^ M,  p^ = {{rho}} / (2 {{beta}}),
+//   F_E = F_rho (1 / (2 (gamma - 1) beta_ln) - {{|u|^2}} / 2) + {{u}} . F_m.
+__device__ inline void ec_flux_contra(const double a[6], const double b[6], double M0, double M1, double M2,
+                                      double gm1, double f[5]) {
+  double rho_ln, inv_beta_ln, p_hat;
+  ec_means(a[0], b[0], a[4], b[4], rho_ln, inv_beta_ln, p_hat);
+  const double u = 0.5 * (a[1] + b[1]), v = 0.5 * (a[2] + b[2]), w = 0.5 * (a[3] + b[3]);
+  const double q2 = 0.5 * (a[5] + b[5]);
+  const double F1 = rho_ln * (u * M0 + v * M1 + w * M2);
+  f[0] = F1;
+  f[1] = F1 * u + p_hat * M0;
+  f[2] = F1 * v + p_hat * M1;
+  f[3] = F1 * w + p_hat * M2;
+  f[4] = F1 * (0.5 / gm1 * inv_beta_ln - 0.5 * q2) + f[1] * u + f[2] * v + f[3] * w;
+}
+
+// Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with unit
+// normal n (L on the side n points away from; primitives (rho, u, v, w, p)
+// and total energies E), linearised at the Roe average (sqrt(rho)-weighted u
+// and H = (E + p) / rho, rho~ = sqrt(rho_L rho_R), a~^2 = (gamma - 1)(H~ - |u~|^2/2)):
+// acoustic waves u~.n -+ a~ with alpha = ([[p]] -+ rho~ a~ [[u.n]]) / (2 a~^2),
+// r = (1, u~ -+ a~ n, H~ -+ (u~.n) a~) and Harten-Hyman |lambda|; the entropy
+// wave u~.n with alpha = [[rho]] - [[p]] / a~^2, r = (1, u~, |u~|^2 / 2); the
+// shear wave u~.n with rho~ (0, [[u]]_t, u~ . [[u]]_t), [[u]]_t = [[u]] - [[u.n]] n.
+__device__ inline void roe_dissipation_normal(const double L[5], double EL, const double R[5], double ER,
+                                              const double n[3], double gamma, double D[5]) {
+  const double sl = sqrt(L[0]), sr = sqrt(R[0]);
+  const double isum = 1.0 / (sl + sr);
+  const double wl = sl * isum, wr = sr * isum;
+  double ut[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ut[c] = wl * L[1 + c] + wr * R[1 + c];
+  const double H = wl * (EL + L[4]) / L[0] + wr * (ER + R[4]) / R[0];
+  const double q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const double a2 = (gamma - 1.0) * (H - 0.5 * q2);
+  const double a = sqrt(a2);
+  const double rho = sl * sr;
+  const double un = ut[0] * n[0] + ut[1] * n[1] + ut[2] * n[2];
+  const double dp = R[4] - L[4];
+  double du[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) du[c] = R[1 + c] - L[1 + c];
+  const double dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const double al1 = (dp - rho * a * dun) / (2.0 * a2);
+  const double al5 = (dp + rho * a * dun) / (2.0 * a2);
+  const double al2 = (R[0] - L[0]) - dp / a2;
+  const double unl = L[1] * n[0] + L[2] * n[1] + L[3] * n[2], unr = R[1] * n[0] + R[2] * n[1] + R[3] * n[2];
+  const double cl = sqrt(gamma * L[4] / L[0]), cr = sqrt(gamma * R[4] / R[0]);
+  const double l1 = hh_abs(un - a, unl - cl, unr - cr);
+  const double l5 = hh_abs(un + a, unl + cl, unr + cr);
+  const double l2 = fabs(un);
+  const double t1 = l1 * al1, t5 = l5 * al5, t2 = l2 * al2, ts = l2 * rho;
+  double udt = 0.0;
+  D[0] = t1 + t2 + t5;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double sh = du[c] - dun * n[c];
+    udt += ut[c] * sh;
+    D[1 + c] = (t1 + t2 + t5) * ut[c] + (t5 - t1) * a * n[c] + ts * sh;
+  }
+  D[4] = t1 * (H - un * a) + t2 * (0.5 * q2) + t5 * (H + un * a) + ts * udt;
+}
+
 // ---------------------------------------------------------------- metrics
 template <int N>
 __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __restrict__ X,
@@ -254,7 +320,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
 }
 
 // ------------------------------------------------------- right-hand side / RK
-template <int N, bool RK, bool VISC>
+template <int N, bool RK, bool VISC, bool EC>
 __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs_curv(
     const double* __restrict__ U, const double* __restrict__ ffv, double* __restrict__ out,
     double* __restrict__ U_out, DevMesh mesh, DevPhys ph, DevBasis basis, Stage st,
@@ -287,11 +353,6 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   // P1: own state; face lanes fetch the neighbour's face node (registers are
   // the limit of this kernel: metric terms, the neighbour's state and the own
   // primitives are fetched again where they are used, from L2 and LDS)
-  long long nb = -1;  // -1: the face is a wall
-  if (face_lane) {
-    const FaceTask<N> ft(tid);
-    nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
-  }
   if (active) {
     double u0[5];
     load_state(U, stride, e * NN + tid, u0);
@@ -301,12 +362,18 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     sp[1][tid] = P.u;
     sp[2][tid] = P.v;
     sp[3][tid] = P.w;
-    sp[4][tid] = P.p;
-    sp[5][tid] = P.e;
+    sp[4][tid] = EC ? 0.5 * P.rho / P.p : P.p;
+    sp[5][tid] = EC ? P.u * P.u + P.v * P.v + P.w * P.w : P.e;
     if (VISC) sT[tid] = P.T;
   }
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-  if (VISC && face_lane && nb >= 0) load_state(U, stride, nb * NN + FaceTask<N>(tid).nb_node(), sn);
+  bool fwall1 = true;  // the face task's face is a wall (P1b)
+  if (VISC && face_lane) {
+    const FaceTask<N> ft(tid);
+    const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
+    fwall1 = nb < 0;
+    if (!fwall1) load_state(U, stride, nb * NN + ft.nb_node(), sn);
+  }
   __syncthreads();
 
   // P1b: BR1 lifting terms of the face nodes
@@ -316,7 +383,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       const int lo = ft.own_node();
       const double qo[4] = {sp[1][lo], sp[2][lo], sp[3][lo], sT[lo]};
       double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};  // isothermal no-slip wall
-      if (nb >= 0) {
+      if (!fwall1) {
         const Prim Pn = primitives(sn, ph);
         qs[0] = 0.5 * (qo[0] + Pn.u);
         qs[1] = 0.5 * (qo[1] + Pn.v);
@@ -379,27 +446,47 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       const int base = d == 0 ? NP * (j + NP * k) : (d == 1 ? i + NF * k : i + NP * j);
       const int step = d == 0 ? 1 : (d == 1 ? NP : NF);
       double ac[5] = {0, 0, 0, 0, 0}, av[4] = {0, 0, 0, 0};
+      if constexpr (EC) {
+        // not unrolled: the pair flux is long, and unrolled copies keep too
+        // many values live
+#pragma unroll 1
+        for (int m = 0; m < NP; ++m) {
+          const int nm = base + step * m;
+          const double Dm = sD[idx][m];
+          const double m0 = 0.5 * (M0 + sM[0][nm]), m1 = 0.5 * (M1 + sM[1][nm]), m2 = 0.5 * (M2 + sM[2][nm]);
+          const double B6[6] = {sp[0][nm], sp[1][nm], sp[2][nm], sp[3][nm], sp[4][nm], sp[5][nm]};
+          double f[5];
+          ec_flux_contra(A, B6, m0, m1, m2, ph.gm1, f);
 #pragma unroll
-      for (int m = 0; m < NP; ++m) {
-        const int nm = base + step * m;
-        const double Dm = sD[idx][m];
-        const double rho = 0.5 * (A[0] + sp[0][nm]);
-        const double uu = 0.5 * (A[1] + sp[1][nm]);
-        const double vv = 0.5 * (A[2] + sp[2][nm]);
-        const double ww = 0.5 * (A[3] + sp[3][nm]);
-        const double pp = 0.5 * (A[4] + sp[4][nm]);
-        const double ee = 0.5 * (A[5] + sp[5][nm]);
-        const double m0 = 0.5 * (M0 + sM[0][nm]), m1 = 0.5 * (M1 + sM[1][nm]), m2 = 0.5 * (M2 + sM[2][nm]);
-        const double Uc = uu * m0 + vv * m1 + ww * m2;
-        const double mass = rho * Uc;
-        ac[0] += Dm * mass;
-        ac[1] += Dm * (mass * uu + pp * m0);
-        ac[2] += Dm * (mass * vv + pp * m1);
-        ac[3] += Dm * (mass * ww + pp * m2);
-        ac[4] += Dm * (mass * ee + pp * Uc);
-        if (VISC) {
+          for (int v = 0; v < 5; ++v) ac[v] += Dm * f[v];
+          if (VISC) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) av[c] += Dm * sfv[c][nm];
+            for (int c = 0; c < 4; ++c) av[c] += Dm * sfv[c][nm];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < NP; ++m) {
+          const int nm = base + step * m;
+          const double Dm = sD[idx][m];
+          const double m0 = 0.5 * (M0 + sM[0][nm]), m1 = 0.5 * (M1 + sM[1][nm]), m2 = 0.5 * (M2 + sM[2][nm]);
+          const double rho = 0.5 * (A[0] + sp[0][nm]);
+          const double uu = 0.5 * (A[1] + sp[1][nm]);
+          const double vv = 0.5 * (A[2] + sp[2][nm]);
+          const double ww = 0.5 * (A[3] + sp[3][nm]);
+          const double pp = 0.5 * (A[4] + sp[4][nm]);
+          const double ee = 0.5 * (A[5] + sp[5][nm]);
+          const double Uc = uu * m0 + vv * m1 + ww * m2;
+          const double mass = rho * Uc;
+          ac[0] += Dm * mass;
+          ac[1] += Dm * (mass * uu + pp * m0);
+          ac[2] += Dm * (mass * vv + pp * m1);
+          ac[3] += Dm * (mass * ww + pp * m2);
+          ac[4] += Dm * (mass * ee + pp * Uc);
+          if (VISC) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) av[c] += Dm * sfv[c][nm];
+          }
         }
       }
       ut[0] -= 2.0 * ac[0];
@@ -410,9 +497,11 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   }
 
 
-  // P4: surface terms (face lanes)
+  // P4: surface terms (face lanes); the neighbour index is formed again here
+  // rather than held through the sweeps
   if (face_lane) {
     const FaceTask<N> ft(tid);
+    const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
     const int lo = ft.own_node();
     // one normal per face: that of the element below it (own on an upper face,
     // the neighbour's on a lower face), so the two sides' fluxes are exact
@@ -424,39 +513,92 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     const long long gi = (ft.up || fwall) ? e * NN + lo : nb * NN + ft.nb_node();
 #pragma unroll
     for (int c = 0; c < 3; ++c) s[c] = mesh.geo[(3 * ft.d + c) * stride + gi];
-    const double Ao[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
+    // the neighbour's face node, fetched again (a state of its own, so that
+    // the one of the lifting phase is not held through the sweeps)
+    double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
     if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
     const Prim Pn = primitives(sn, ph);
-    const double An[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
-    const double so[5] = {Ao[0], Ao[0] * Ao[1], Ao[0] * Ao[2], Ao[0] * Ao[3], Ao[0] * Ao[5]};
-    // own contravariant Euler flux
-    const double Uo = Ao[1] * s[0] + Ao[2] * s[1] + Ao[3] * s[2];
-    const double Fo[5] = {Ao[0] * Uo, Ao[0] * Ao[1] * Uo + Ao[4] * s[0], Ao[0] * Ao[2] * Uo + Ao[4] * s[1],
-                          Ao[0] * Ao[3] * Uo + Ao[4] * s[2], (Ao[0] * Ao[5] + Ao[4]) * Uo};
-    // central part: the contravariant Kennedy-Gruber flux of the two sides
-    const double rho = 0.5 * (Ao[0] + An[0]), uu = 0.5 * (Ao[1] + An[1]), vv = 0.5 * (Ao[2] + An[2]);
-    const double ww = 0.5 * (Ao[3] + An[3]), pp = 0.5 * (Ao[4] + An[4]), ee = 0.5 * (Ao[5] + An[5]);
-    const double Uc = uu * s[0] + vv * s[1] + ww * s[2];
-    const double mass = rho * Uc;
-    double Fs[5] = {mass, mass * uu + pp * s[0], mass * vv + pp * s[1], mass * ww + pp * s[2],
-                    mass * ee + pp * Uc};
-    if (fwall) {  // impermeable wall: the interior pressure only
-      Fs[0] = 0.0;
-      Fs[1] = Ao[4] * s[0];
-      Fs[2] = Ao[4] * s[1];
-      Fs[3] = Ao[4] * s[2];
-      Fs[4] = 0.0;
-    } else if (!ph.central) {
-      const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
-      const double co = sqrt(ph.gamma * Ao[4] / Ao[0]), cn = sqrt(ph.gamma * An[4] / An[0]);
-      const double uno = Uo / smag, unn = (An[1] * s[0] + An[2] * s[1] + An[3] * s[2]) / smag;
-      // L = own on an upper face, the neighbour on a lower face; ties go to L
-      const double lo_l = ft.up ? fabs(uno) + co : fabs(unn) + cn;
-      const double lo_r = ft.up ? fabs(unn) + cn : fabs(uno) + co;
-      const double lam = lo_r > lo_l ? lo_r : lo_l;
-      const double h = 0.5 * lam * smag * (ft.up ? 1.0 : -1.0);
+    double Fo[5], Fs[5], vo[3];  // own contravariant Euler flux, surface flux, own velocity
+    if constexpr (EC) {
+      // sp holds (rho, u, v, w, beta, |u|^2): p = rho / (2 beta), E from p and |u|^2
+      const double A6[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
+      const double po = 0.5 * A6[0] / A6[4];
+      const double Eo = po / ph.gm1 + 0.5 * A6[0] * A6[5];
+      vo[0] = A6[1];
+      vo[1] = A6[2];
+      vo[2] = A6[3];
+      const double Uo = A6[1] * s[0] + A6[2] * s[1] + A6[3] * s[2];
+      Fo[0] = A6[0] * Uo;
+      Fo[1] = A6[0] * A6[1] * Uo + po * s[0];
+      Fo[2] = A6[0] * A6[2] * Uo + po * s[1];
+      Fo[3] = A6[0] * A6[3] * Uo + po * s[2];
+      Fo[4] = (Eo + po) * Uo;
+      if (fwall) {  // impermeable wall: the interior pressure only
+        Fs[0] = 0.0;
+        Fs[1] = po * s[0];
+        Fs[2] = po * s[1];
+        Fs[3] = po * s[2];
+        Fs[4] = 0.0;
+      } else {
+        // central part: Chandrashekar's flux contracted with the face normal
+        const double B6[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, 0.5 * Pn.rho / Pn.p, Pn.u * Pn.u + Pn.v * Pn.v + Pn.w * Pn.w};
+        ec_flux_contra(A6, B6, s[0], s[1], s[2], ph.gm1, Fs);
+        if (!ph.central) {
+          const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+          const double ism = 1.0 / smag;
+          const double n[3] = {s[0] * ism, s[1] * ism, s[2] * ism};
+          const double Po5[5] = {A6[0], A6[1], A6[2], A6[3], po}, Pn5[5] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p};
+          double Dr[5];
+          // L = own on an upper face, the neighbour on a lower face
+          if (ft.up)
+            roe_dissipation_normal(Po5, Eo, Pn5, sn[4], n, ph.gamma, Dr);
+          else
+            roe_dissipation_normal(Pn5, sn[4], Po5, Eo, n, ph.gamma, Dr);
 #pragma unroll
-      for (int v = 0; v < 5; ++v) Fs[v] -= h * (sn[v] - so[v]);
+          for (int v = 0; v < 5; ++v) Fs[v] -= 0.5 * smag * Dr[v];
+        }
+      }
+    } else {
+      const double Ao[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
+      const double An[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
+      const double so[5] = {Ao[0], Ao[0] * Ao[1], Ao[0] * Ao[2], Ao[0] * Ao[3], Ao[0] * Ao[5]};
+      vo[0] = Ao[1];
+      vo[1] = Ao[2];
+      vo[2] = Ao[3];
+      const double Uo = Ao[1] * s[0] + Ao[2] * s[1] + Ao[3] * s[2];
+      Fo[0] = Ao[0] * Uo;
+      Fo[1] = Ao[0] * Ao[1] * Uo + Ao[4] * s[0];
+      Fo[2] = Ao[0] * Ao[2] * Uo + Ao[4] * s[1];
+      Fo[3] = Ao[0] * Ao[3] * Uo + Ao[4] * s[2];
+      Fo[4] = (Ao[0] * Ao[5] + Ao[4]) * Uo;
+      // central part: the contravariant Kennedy-Gruber flux of the two sides
+      const double rho = 0.5 * (Ao[0] + An[0]), uu = 0.5 * (Ao[1] + An[1]), vv = 0.5 * (Ao[2] + An[2]);
+      const double ww = 0.5 * (Ao[3] + An[3]), pp = 0.5 * (Ao[4] + An[4]), ee = 0.5 * (Ao[5] + An[5]);
+      const double Uc = uu * s[0] + vv * s[1] + ww * s[2];
+      const double mass = rho * Uc;
+      Fs[0] = mass;
+      Fs[1] = mass * uu + pp * s[0];
+      Fs[2] = mass * vv + pp * s[1];
+      Fs[3] = mass * ww + pp * s[2];
+      Fs[4] = mass * ee + pp * Uc;
+      if (fwall) {  // impermeable wall: the interior pressure only
+        Fs[0] = 0.0;
+        Fs[1] = Ao[4] * s[0];
+        Fs[2] = Ao[4] * s[1];
+        Fs[3] = Ao[4] * s[2];
+        Fs[4] = 0.0;
+      } else if (!ph.central) {
+        const double smag = sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        const double co = sqrt(ph.gamma * Ao[4] / Ao[0]), cn = sqrt(ph.gamma * An[4] / An[0]);
+        const double uno = Uo / smag, unn = (An[1] * s[0] + An[2] * s[1] + An[3] * s[2]) / smag;
+        // L = own on an upper face, the neighbour on a lower face; ties go to L
+        const double lo_l = ft.up ? fabs(uno) + co : fabs(unn) + cn;
+        const double lo_r = ft.up ? fabs(unn) + cn : fabs(uno) + co;
+        const double lam = lo_r > lo_l ? lo_r : lo_l;
+        const double h = 0.5 * lam * smag * (ft.up ? 1.0 : -1.0);
+#pragma unroll
+        for (int v = 0; v < 5; ++v) Fs[v] -= h * (sn[v] - so[v]);
+      }
     }
     double fvo[4] = {0, 0, 0, 0}, fvs[4] = {0, 0, 0, 0};
     if (VISC) {
@@ -467,7 +609,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
         // and of the energy flux only the heat flux
 #pragma unroll
         for (int c = 0; c < 3; ++c) fvs[c] = fvo[c];
-        fvs[3] = fvo[3] - (Ao[1] * fvo[0] + Ao[2] * fvo[1] + Ao[3] * fvo[2]);
+        fvs[3] = fvo[3] - (vo[0] * fvo[0] + vo[1] * fvo[1] + vo[2] * fvo[2]);
       } else {
         const double* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
 #pragma unroll
@@ -541,10 +683,20 @@ hipError_t rhs_curv_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, con
                       const double* ffv, double* out, double* U_out, const Stage& st, int* status,
                       hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(m.nE)), block(CurvCfg<N>::BS);
-  if (p.viscous)
-    hipLaunchKernelGGL((k_rhs_curv<N, RK, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st, status);
-  else
-    hipLaunchKernelGGL((k_rhs_curv<N, RK, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st, status);
+  if (p.ec) {
+    if (p.viscous)
+      hipLaunchKernelGGL((k_rhs_curv<N, RK, true, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
+                         status);
+    else
+      hipLaunchKernelGGL((k_rhs_curv<N, RK, false, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
+                         status);
+  } else if (p.viscous) {
+    hipLaunchKernelGGL((k_rhs_curv<N, RK, true, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
+                       status);
+  } else {
+    hipLaunchKernelGGL((k_rhs_curv<N, RK, false, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
+                       status);
+  }
   return hipGetLastError();
 }
 

@@ -517,36 +517,6 @@ __device__ inline void surface_correction(const double A[6], const double so[5],
 // Entropy-conserving volume flux and Roe surface flux (FP64)
 // ---------------------------------------------------------------------------
 
-// 1 / x for x > 0 of moderate size: the hardware reciprocal estimate refined
-// by two Newton-Raphson steps r <- r + r (1 - x r).
-__device__ inline double rcp_nr(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
-}
-
-// Means of the entropy-conserving flux for one pair: rho_ln and 1 / beta_ln
-// (logarithmic means) and p^ = {{rho}} / (2 {{beta}}).  The logarithmic mean of
-// positive a, b is (a - b) / (ln a - ln b) = (a + b) / (2 F), F = atanh(f) / f,
-// f = (a - b) / (a + b) (ln(a / b) = 2 atanh f).  For f^2 < 1e-4 F is its
-// series 1 + f^2/3 + f^4/5 + f^6/7 and 1 / F the series
-// 1 - f^2/3 - 4 f^4/45 - 44 f^6/945 (first dropped terms below 1.2e-17 and
-// 3.1e-18), so the common case costs two reciprocals and no logarithm.
-__device__ inline void ec_means(double ra, double rb, double ba, double bb, double& rho_ln,
-                                double& inv_beta_ln, double& p_hat) {
-  const double sr = ra + rb, sb = ba + bb;
-  const double ir = rcp_nr(sr), ib = rcp_nr(sb);
-  const double fr = (ra - rb) * ir, fb = (ba - bb) * ib;
-  const double ur = fr * fr, ub = fb * fb;
-  rho_ln = 0.5 * sr * (1.0 - ur * (1.0 / 3.0 + ur * (4.0 / 45.0 + ur * (44.0 / 945.0))));
-  inv_beta_ln = 2.0 * ib * (1.0 + ub * (1.0 / 3.0 + ub * (0.2 + ub * (1.0 / 7.0))));
-  if (ur >= 1e-4) rho_ln = 0.5 * sr * fr / atanh(fr);
-  if (ub >= 1e-4) inv_beta_ln = 2.0 * ib * atanh(fb) / fb;
-  p_hat = 0.5 * sr * ib;
-}
-
 // Chandrashekar's kinetic-energy-preserving, entropy-conserving two-point flux
 // along d (paper Sec. 4 names it as the production volume flux).  a, b =
 // (rho, u), (v, w), (beta, |u|^2) with beta = rho / (2 p); {{x}} arithmetic and
@@ -602,15 +572,6 @@ __device__ inline void volume_sweep_ec(const double2 (&own)[3], int i, int j, in
       av[3] += Dim * f23.y;
     }
   }
-}
-
-// |lambda| with Harten's entropy correction in the Harten-Hyman form:
-// (lambda^2 + delta^2) / (2 delta) where |lambda| < delta,
-// delta = max(0, lambda - lambda_L, lambda_R - lambda).
-__device__ inline double hh_abs(double lam, double lam_L, double lam_R) {
-  double delta = fmax(lam - lam_L, lam_R - lam);
-  delta = delta > 0.0 ? delta : 0.0;
-  return fabs(lam) < delta ? (lam * lam + delta * delta) / (2.0 * delta) : fabs(lam);
 }
 
 // Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with normal e_d

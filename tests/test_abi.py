@@ -162,7 +162,7 @@ def test_wall_face_count(L):
 
 def test_curved_mesh_validation(L):
     """Curved elements (node coordinates given): periodic or isothermal-wall
-    ends, FP64, Kennedy-Gruber only; faces may be absent; non-finite
+    ends, FP64 (either flux pair); faces may be absent; non-finite
     coordinates are rejected.  Host only."""
     from paper_2606_18927_amd.workloads import warped_nodes
     N, n = 3, (2, 2, 2)
@@ -189,7 +189,7 @@ def test_curved_mesh_validation(L):
     L.dg_free(ctx)
     nd = 8 * 64
     assert size.value >= plain.value + 10 * nd * 8  # metric terms: 10 values per DOF
-    for bad, code in ((dict(precision=1), dgsem.DG_EUNSUPPORTED), (dict(flux=1), dgsem.DG_EUNSUPPORTED)):
+    for bad, code in ((dict(precision=1), dgsem.DG_EUNSUPPORTED),):
         d, keep = desc()
         assert _init(L, d, _phys(**bad))[0] == code, bad
     d, keep = desc(bc=(0, 1, 0))  # isothermal walls are fine

@@ -52,25 +52,29 @@ def _warped(N, n, amp):
     return workloads.warped_nodes(xi, n, amp=amp)
 
 
-@pytest.mark.parametrize("N,n,amp,viscous,central,suth", [
-    (3, (2, 3, 2), 0.08, True, False, False),
-    (5, (2, 2, 3), 0.05, True, False, False),
-    (7, (2, 2, 2), 0.05, True, False, False),
-    (3, (3, 2, 2), 0.08, False, False, False),
-    (5, (2, 2, 2), 0.08, True, True, False),
-    (3, (2, 2, 2), 0.08, True, False, True),
+@pytest.mark.parametrize("N,n,amp,viscous,central,suth,flux", [
+    (3, (2, 3, 2), 0.08, True, False, False, "kg_llf"),
+    (5, (2, 2, 3), 0.05, True, False, False, "kg_llf"),
+    (7, (2, 2, 2), 0.05, True, False, False, "kg_llf"),
+    (3, (3, 2, 2), 0.08, False, False, False, "kg_llf"),
+    (5, (2, 2, 2), 0.08, True, True, False, "kg_llf"),
+    (3, (2, 2, 2), 0.08, True, False, True, "kg_llf"),
+    (3, (2, 3, 2), 0.08, True, False, False, "ec_roe"),
+    (5, (2, 2, 3), 0.05, False, False, False, "ec_roe"),
+    (7, (2, 2, 2), 0.05, True, False, True, "ec_roe"),
+    (5, (2, 2, 2), 0.08, False, True, False, "ec_roe"),
 ])
-def test_curved_rhs_against_oracle(N, n, amp, viscous, central, suth):
+def test_curved_rhs_against_oracle(N, n, amp, viscous, central, suth, flux):
     need_gpu()
-    say("curved rhs", N, n, amp, viscous, central, suth)
+    say("curved rhs", N, n, amp, viscous, central, suth, flux)
     X = _warped(N, n, amp)
     mesh = cv.CurvMesh(N, torch.as_tensor(X))
     g = Gas(gamma=1.4, R=1.0, mu=0.02, Pr=0.72, sutherland=True, T_ref=1.0, S=0.4) if suth else GAS
     U = random_state(mesh, g.gamma, g.R, np.random.default_rng(90 + N)).numpy()
-    S = _solver(N, X, g, viscous=viscous, central_only=central)
+    S = _solver(N, X, g, viscous=viscous, central_only=central, flux=flux)
     got = S.eval_rhs(to_dev(U)).cpu().numpy()
     S.sync()
-    ref = cv.rhs(torch.as_tensor(U), mesh, g, viscous=viscous, central_only=central).numpy()
+    ref = cv.rhs(torch.as_tensor(U), mesh, g, viscous=viscous, central_only=central, flux=flux).numpy()
     e = rel_l2(got, ref)
     say("  rel L2", e)
     assert np.all(e < TOL)
@@ -109,6 +113,26 @@ def test_free_stream_preserved_on_warped_mesh():
     assert np.abs(out).max() < 1e-12 * scale
 
 
+def test_curved_ec_entropy_conservation():
+    """The GPU's Euler central entropy-conserving operator on a warped mesh:
+    the total entropy rate sum w J v . Ut vanishes to rounding (J from the
+    oracle's metric terms, v the entropy variables of the state)."""
+    from oracle.physics import entropy_variables, primitives
+    need_gpu()
+    N = 5
+    X = _warped(N, (2, 2, 3), 0.08)
+    mesh = cv.CurvMesh(N, torch.as_tensor(X))
+    U = random_state(mesh, GAS.gamma, GAS.R, np.random.default_rng(31)).numpy()
+    S = _solver(N, X, GAS, viscous=False, central_only=True, flux="ec_roe")
+    out = S.eval_rhs(to_dev(U)).cpu().numpy().reshape(U.shape)
+    S.sync()
+    v = entropy_variables(primitives(torch.as_tensor(U), GAS), GAS)
+    wq = mesh.quadrature_weights().numpy()
+    terms = sum(wq * v[k].numpy() * out[k] for k in range(5))
+    say("entropy rate", terms.sum(), "of", np.abs(terms).sum())
+    assert abs(terms.sum()) < 1e-12 * np.abs(terms).sum()
+
+
 def test_curved_rk_steps():
     need_gpu()
     wl = workloads.WORKLOADS["tgv_n3_4x4x4_curved"]
@@ -128,24 +152,25 @@ def test_curved_rk_steps():
 
 # ------------------------------------------------- wavy-walled channels
 
-@pytest.mark.parametrize("N,n,viscous,suth", [
-    (3, (2, 3, 2), True, False),
-    (5, (2, 2, 2), True, False),
-    (3, (3, 2, 2), False, False),
-    (5, (2, 3, 2), True, True),
+@pytest.mark.parametrize("N,n,viscous,suth,flux", [
+    (3, (2, 3, 2), True, False, "kg_llf"),
+    (5, (2, 2, 2), True, False, "kg_llf"),
+    (3, (3, 2, 2), False, False, "kg_llf"),
+    (5, (2, 3, 2), True, True, "kg_llf"),
+    (5, (2, 3, 2), True, False, "ec_roe"),
 ])
-def test_wavy_channel_rhs_against_oracle(N, n, viscous, suth):
+def test_wavy_channel_rhs_against_oracle(N, n, viscous, suth, flux):
     need_gpu()
-    say("wavy channel rhs", N, n, viscous, suth)
+    say("wavy channel rhs", N, n, viscous, suth, flux)
     X = workloads.wavy_channel_nodes(dgsem.lgl(N)[0], n, amp=0.06)
     bc = ("periodic", "wall", "periodic")
     mesh = cv.CurvMesh(N, torch.as_tensor(X), bc=bc, T_wall=1.3)
     g = Gas(gamma=1.4, R=1.0, mu=0.02, Pr=0.72, sutherland=True, T_ref=1.0, S=0.4) if suth else GAS
     U = random_state(mesh, g.gamma, g.R, np.random.default_rng(60 + N)).numpy()
-    S = _solver(N, X, g, bc=bc, T_wall=1.3, viscous=viscous)
+    S = _solver(N, X, g, bc=bc, T_wall=1.3, viscous=viscous, flux=flux)
     got = S.eval_rhs(to_dev(U)).cpu().numpy()
     S.sync()
-    ref = cv.rhs(torch.as_tensor(U), mesh, g, viscous=viscous).numpy()
+    ref = cv.rhs(torch.as_tensor(U), mesh, g, viscous=viscous, flux=flux).numpy()
     e = rel_l2(got, ref)
     say("  rel L2", e)
     assert np.all(e < TOL)
@@ -297,7 +322,7 @@ def test_curved_rejected_combinations():
     need_gpu()
     N = 3
     X = _warped(N, (2, 2, 2), 0.05)
-    for kw in (dict(precision="mixed"), dict(flux="ec_roe")):
+    for kw in (dict(precision="mixed"),):
         with pytest.raises(dgsem.DgsemError) as ei:
             _solver(N, X, GAS, **kw)
         assert ei.value.status == dgsem.DG_EUNSUPPORTED
