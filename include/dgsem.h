@@ -73,7 +73,7 @@ typedef enum {
                                  mu being the viscosity at T_ref; T_ref and S in the units
                                  of T; taken at each node's temperature (at a wall: the
                                  interior face node's; in the wall model: the wall
-                                 temperature's).  DG_FP64 only; no adjoint               */
+                                 temperature's).  DG_FP64 only; the adjoint covers it      */
 
 typedef struct dg_ctx dg_ctx;
 
@@ -171,8 +171,9 @@ dg_status dg_rk_step(dg_ctx* ctx, double t, double dt, int nsteps);
 
 /* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs.  Needs a
  * workspace bound with_adjoint.  FP64 arithmetic.  The VJP calls cover the
- * Kennedy-Gruber / Lax-Friedrichs fluxes with constant viscosity and
- * isothermal or periodic ends; other contexts get DG_EUNSUPPORTED.          */
+ * Kennedy-Gruber / Lax-Friedrichs fluxes on axis-aligned elements with
+ * isothermal or periodic ends (either viscosity law); other contexts get
+ * DG_EUNSUPPORTED.                                                          */
 dg_status dg_eval_rhs_vjp(dg_ctx* ctx, const double* U_dev, const double* lam_dev,
                           double* Ubar_dev, double t);
 

@@ -287,7 +287,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 
   // P2: node lanes
   const bool visc = ph.viscous != 0;
-  const double mu = ph.mu, kappa = ph.kappa;
+  // viscosity and conductivity at this node's temperature (Sutherland's law,
+  // or constant: r = 1)
+  const double Tn = sT[le][l];
+  const double rT = viscosity_ratio(ph, Tn);
+  const double mu = ph.mu * rT, kappa = ph.kappa * rT;
   // forward BR1 gradients g[3 q + d] of q = (u, v, w, T) at this node
   double g[12];
 #pragma unroll
@@ -381,9 +385,20 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
     for (int d = 0; d < 3; ++d) gbar[(9 + d) * stride + idx] = gT[d];
   }
+  // Sutherland's law: tau and q scale with r(T), so T gets
+  // (d ln r / dT) (tbar : tau + sum_d Fv_d,E q_d), d ln r / dT = 3 / (2 T) - 1 / (T + S)
+  double Tb = 0.0;
+  if (visc && ph.suth) {
+    double st = 0.0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) st += tb[c] * tau[c];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) st += gT[d] * g[9 + d];
+    Tb = (1.5 / Tn - 1.0 / (Tn + ph.suth_S)) * st;
+  }
   double s[5];
   load_state(U, stride, idx, s);
-  prim_vjp(s, Pb, 0.0, ph, Ub);
+  prim_vjp(s, Pb, Tb, ph, Ub);
 #pragma unroll
   for (int v = 0; v < 5; ++v) ubar[v * stride + idx] = Ub[v];
 }

@@ -267,8 +267,6 @@ dg_status need_adjoint(dg_ctx* c) {
     return fail(c, DG_EUNSUPPORTED, "the adjoint is built for the Kennedy-Gruber / Lax-Friedrichs fluxes");
   if (c->wall_model) return fail(c, DG_EUNSUPPORTED, "the adjoint does not cover the wall model");
   if (c->curvilinear) return fail(c, DG_EUNSUPPORTED, "the adjoint is built for axis-aligned elements");
-  if (c->phys.viscosity != DG_VISC_CONSTANT)
-    return fail(c, DG_EUNSUPPORTED, "the adjoint is built for constant viscosity");
   return DG_OK;
 }
 

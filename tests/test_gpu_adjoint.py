@@ -1,6 +1,7 @@
 """Adjoint (vector-Jacobian product) of the HIP operator against the oracle (GPU).
 
-* dg_eval_rhs_vjp vs the oracle's reverse-mode VJP, per variable rel L2;
+* dg_eval_rhs_vjp vs the oracle's reverse-mode VJP, per variable rel L2
+  (constant viscosity and Sutherland's law);
 * <Ubar_gpu, v> vs <lam, (dL/dU) v> with the oracle's complex-step JVP;
 * dg_rk_step_vjp vs the oracle's reverse mode through one RK step;
 * the kinetic-energy gradient of a short rollout (checkpointed) vs the oracle;
@@ -60,6 +61,35 @@ def test_eval_rhs_vjp_against_oracle(N, n, bc):
     e = rel_l2(got, ref)
     say("  rel L2", e)
     assert np.all(e < TOL)
+
+
+@pytest.mark.parametrize("N,n,bc", [
+    (3, (3, 2, 3), ("periodic",) * 3),
+    (5, (2, 3, 2), ("periodic", "wall", "periodic")),
+])
+def test_eval_rhs_vjp_sutherland_against_oracle(N, n, bc):
+    """Sutherland's law (S / T_ref = 110.4 / 288.15 at T ~ 1): the adjoint's
+    temperature cotangent through mu(T) and kappa(T), against the oracle's
+    reverse mode, and the dot-product test with its complex-step JVP."""
+    from oracle.physics import Gas
+    need_gpu()
+    mesh, g0, U, lam = _random_case(N, n, bc, seed=41 + N, mu=0.02)
+    g = Gas(gamma=g0.gamma, R=g0.R, mu=g0.mu, Pr=g0.Pr, sutherland=True, T_ref=1.0, S=110.4 / 288.15)
+    S = _solver(mesh, g, sutherland=(g.T_ref, g.S))
+    got = S.eval_rhs_vjp(to_dev(U), to_dev(lam)).cpu().numpy()
+    S.sync()
+    ref = rhs_vjp(torch.as_tensor(U), torch.as_tensor(lam), mesh, g).numpy()
+    e = rel_l2(got, ref)
+    say("  sutherland vjp rel L2", e)
+    assert np.all(e < TOL)
+    # the law's derivative matters: the constant-viscosity VJP differs
+    ref0 = rhs_vjp(torch.as_tensor(U), torch.as_tensor(lam), mesh, g0).numpy()
+    assert np.max(rel_l2(ref0, ref)) > 1e3 * TOL
+    v = np.random.default_rng(7).standard_normal(U.shape)
+    jv = rhs_jvp_cs(torch.as_tensor(U), torch.as_tensor(v), mesh, g).numpy()
+    a, b = float((got.reshape(U.shape) * v).sum()), float((lam * jv).sum())
+    say("  <Ubar, v> vs <lam, J v>", a, b)
+    assert abs(a - b) <= 1e-11 * max(abs(b), float(np.abs(lam * jv).sum()) * 1e-3)
 
 
 @pytest.mark.parametrize("viscous,central", [(False, False), (False, True), (True, True)])

@@ -6,7 +6,7 @@ Right-hand side: relative L2 <= 1e-12 per variable on random states (T varies
 by about 40 % across nodes) at N = 3, 5, 7, periodic and between isothermal
 walls, with both flux pairs; five RK steps; the wall-model stress and the
 operator with wall-model ends (mu at the wall temperature); the rejected
-combinations (mixed precision, the adjoint, bad constants).
+combinations (mixed precision, bad constants).
 """
 
 import numpy as np
@@ -121,11 +121,7 @@ def test_sutherland_rejected_combinations():
     with pytest.raises(dgsem.DgsemError) as ei:
         _solver(mesh, g, precision="mixed")
     assert ei.value.status == dgsem.DG_EUNSUPPORTED
-    S = _solver(mesh, g, with_adjoint=True)
-    U = to_dev(_state(mesh, np.random.default_rng(1)))
-    with pytest.raises(dgsem.DgsemError) as ei:
-        S.eval_rhs_vjp(U, U)
-    assert ei.value.status == dgsem.DG_EUNSUPPORTED
+    # (the adjoint covers Sutherland's law: tests/test_gpu_adjoint.py)
     for T_ref, Sg in ((0.0, 0.3), (1.0, -0.1), (float("nan"), 0.3)):
         spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall, mesh.wm_node)
         with pytest.raises(dgsem.DgsemError) as ei:

@@ -86,3 +86,20 @@ def test_uniform_temperature_reduces_to_constant_viscosity(walls):
     # and the viscosity matters for this state
     g2 = Gas(gamma=1.4, R=1.0, mu=0.01, Pr=0.72)
     assert torch.linalg.norm(rhs(U, mesh, g2)[1] - b[1]) > 1e-6 * torch.linalg.norm(b[1])
+
+
+def test_reverse_mode_through_sutherland_matches_complex_step():
+    """<(dL/dU)^T lam, v> = <lam, (dL/dU) v>: the oracle's reverse mode through
+    mu(T) and kappa(T) against its complex-step derivative (which evaluates the
+    law at complex temperatures)."""
+    from oracle.adjoint import rhs_jvp_cs, rhs_vjp
+    rng = np.random.default_rng(44)
+    mesh = Mesh(3, tuple(random_faces(n, 0.0, 2.0, rng) for n in (3, 2, 2)))
+    g = Gas(gamma=1.4, R=1.0 / (1.4 * 0.01), mu=0.02, Pr=0.72, sutherland=True, T_ref=1.0, S=110.4 / 288.15)
+    from _cases import random_state
+    U = random_state(mesh, g.gamma, g.R, rng, vel_amp=1.0, p_mean=1.0 / (1.4 * 0.01), p_amp=0.05)
+    lam = torch.tensor(rng.standard_normal(U.shape))
+    v = torch.tensor(rng.standard_normal(U.shape))
+    a = (rhs_vjp(U, lam, mesh, g) * v).sum().item()
+    b = (lam * rhs_jvp_cs(U, v, mesh, g)).sum().item()
+    assert abs(a - b) <= 1e-13 * abs(b)
