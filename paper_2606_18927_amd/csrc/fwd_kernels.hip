@@ -211,6 +211,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
   __shared__ R sD[NP * Gm::DS];
   __shared__ V2 sq[EPB][2][EB];  // (u, v), (w, T - T_ref)
   __shared__ R ssq[EPB][6][4][NF];
+  constexpr bool MIXED = sizeof(R) == 4;
+  // mixed precision: the FP64 (u, v, w, T) of every node, for the lifting terms
+  __shared__ double sqd[MIXED ? EPB : 1][4][MIXED ? NN : 1];
 
   const int tid = threadIdx.x;
   const long long nE = mesh.nE;
@@ -224,11 +227,10 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
   int ex0 = 0, ey0 = 0, ez0 = 0;
   elem_coords(e0 < nE ? e0 : 0, mesh, ex0, ey0, ez0);
 
-  // P1: node lanes stage (u, v, w, T - T_ref) in LDS; face lanes fetch the
-  // neighbour state and form the BR1 lifting corrections in FP64 (after the
-  // barrier with the own values from LDS in FP64 mode; mixed precision
-  // recovers the own FP64 values from U)
-  constexpr bool MIXED = sizeof(R) == 4;
+  // P1: node lanes stage (u, v, w, T - T_ref) in LDS (and, in mixed
+  // precision, an FP64 copy of (u, v, w, T)); face lanes fetch the
+  // neighbour state and form the BR1 lifting corrections in FP64 after the
+  // barrier, with the own values from LDS
   const bool face_lane = tid < n_face_tasks<N>();
   const bool face_ok = face_lane && (EPB == 1 ? e0 : e0 + FaceTask<N>(face_lane ? tid : 0).le) < nE;
   // the own state is fetched first, so that it and the neighbour's face node
@@ -252,15 +254,6 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
     fwall = nb < 0;
     if (!fwall) load_state(U, stride, nb * NN + ft.nb_node(), sn);
-    if (MIXED) {
-      double so[5];
-      load_state(U, stride, te * NN + ft.own_node(), so);
-      double corr[4];
-      lifting_correction(primitives(so, ph), primitives(sn, ph), fwall, mesh.T_wall, ft.up,
-                         basis.inv_w_end, corr);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
-    }
   }
   if (node_ok) {
     const int i = node % NP, j = (node / NP) % NP, k = node / NF;
@@ -270,15 +263,31 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     const int l = Gm::lds(i, j, k);
     sq[nle][0][l] = V2{static_cast<R>(P.u), static_cast<R>(P.v)};
     sq[nle][1][l] = V2{static_cast<R>(P.w), static_cast<R>(P.T - T_ref)};
+    if (MIXED) {
+      sqd[nle][0][node] = P.u;
+      sqd[nle][1][node] = P.v;
+      sqd[nle][2][node] = P.w;
+      sqd[nle][3][node] = P.T;
+    }
   }
   if (tid < NP * NP) sD[(tid / NP) * Gm::DS + tid % NP] = static_cast<R>(dval);
   __syncthreads();
-  if (!MIXED) {
+  {
     if (face_ok) {
       const FaceTask<N> ft(tid);
-      const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
-      const V2 uv = sq[ft.le][0][lo], wT = sq[ft.le][1][lo];
-      const double qo[4] = {uv.x, uv.y, wT.x, wT.y};
+      double qo[4];
+      if (MIXED) {
+        const int on = ft.own_node();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qo[c] = sqd[ft.le][c][on];
+      } else {
+        const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
+        const V2 uv = sq[ft.le][0][lo], wT = sq[ft.le][1][lo];
+        qo[0] = uv.x;
+        qo[1] = uv.y;
+        qo[2] = wT.x;
+        qo[3] = wT.y;
+      }
       double qs[4];
       wall_lifting_value(mesh, ft.d, qo, qs);
       if (!fwall) {
