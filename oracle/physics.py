@@ -221,7 +221,7 @@ def ln_mean(a, b):
     s = a + b
     f = (a - b) / s
     u = f * f
-    small = u < 1e-4
+    small = _re(u) < 1e-4
     fs = torch.where(small, torch.ones_like(f), f)
     F = torch.where(small, 1.0 + u / 3.0 + u * u / 5.0 + u * u * u / 7.0, torch.atanh(fs) / fs)
     return s / (2.0 * F)
@@ -291,11 +291,12 @@ def roe_waves(L: Prim, R: Prim, d: int, gas: Gas):
 
 def harten_hyman_abs(lam, lam_L, lam_R):
     """|lambda| with the entropy correction: (lambda^2 + delta^2) / (2 delta) where
-    |lambda| < delta = max(0, lambda - lambda_L, lambda_R - lambda)."""
-    delta = torch.clamp(torch.maximum(lam - lam_L, lam_R - lam), min=0.0)
-    small = torch.abs(lam) < delta
+    |lambda| < delta = max(0, lambda - lambda_L, lambda_R - lambda).  Comparisons
+    take the real part and |.| is sign(Re z) z, so complex steps pass through."""
+    delta = rmax(rmax(lam - lam_L, lam_R - lam), torch.zeros_like(lam))
+    small = _re(rabs(lam)) < _re(delta)
     dsafe = torch.where(small, delta, torch.ones_like(delta))
-    return torch.where(small, (lam * lam + delta * delta) / (2.0 * dsafe), torch.abs(lam))
+    return torch.where(small, (lam * lam + delta * delta) / (2.0 * dsafe), rabs(lam))
 
 
 def roe_flux(L: Prim, R: Prim, d: int, gas: Gas, central_only: bool = False, entropy_fix: bool = True):
@@ -305,7 +306,7 @@ def roe_flux(L: Prim, R: Prim, d: int, gas: Gas, central_only: bool = False, ent
     if central_only:
         return f
     lam, alpha, r = roe_waves(L, R, d, gas)
-    absl = [torch.abs(x) for x in lam]
+    absl = [rabs(x) for x in lam]
     if entropy_fix:
         cL, cR = L.c(gas), R.c(gas)
         absl[0] = harten_hyman_abs(lam[0], L.vel[d] - cL, R.vel[d] - cR)
