@@ -63,8 +63,8 @@ typedef enum {
 #define DG_FLUX_EC_ROE 1  /* the paper's production pair (Sec. 4): Chandrashekar's
                              entropy-conserving volume flux; Roe surface flux with
                              Harten's entropy correction (Harten-Hyman form), its
-                             central part the Chandrashekar flux.  DG_FP64 only; no
-                             adjoint (the VJP calls return DG_EUNSUPPORTED)            */
+                             central part the Chandrashekar flux.  DG_FP64 only; the
+                             adjoint covers it                                         */
 
 /* Viscosity laws (dg_physics.viscosity). */
 #define DG_VISC_CONSTANT 0    /* mu constant                                              */
@@ -170,10 +170,11 @@ dg_status dg_eval_lift(dg_ctx* ctx, const double* U_dev, double* grad_dev);
 dg_status dg_rk_step(dg_ctx* ctx, double t, double dt, int nsteps);
 
 /* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs.  Needs a
- * workspace bound with_adjoint.  FP64 arithmetic.  The VJP calls cover the
- * Kennedy-Gruber / Lax-Friedrichs fluxes on axis-aligned elements with
- * isothermal or periodic ends (either viscosity law); other contexts get
- * DG_EUNSUPPORTED.                                                          */
+ * workspace bound with_adjoint.  FP64 arithmetic.  The VJP calls cover
+ * axis-aligned elements with isothermal or periodic ends (either flux pair,
+ * either viscosity law); curved elements and the wall model get
+ * DG_EUNSUPPORTED.  Non-smooth points (|.|, max, the entropy correction's
+ * branch) take the derivative of the branch the values select.              */
 dg_status dg_eval_rhs_vjp(dg_ctx* ctx, const double* U_dev, const double* lam_dev,
                           double* Ubar_dev, double t);
 

@@ -12,7 +12,9 @@
 //             part of Ubar that does not pass through the lifting:
 //               * volume split form: for each line pair (i, m),
 //                 Pbar_i += -2 s_d J1(P_i, P_m)^T (D_im lam_i + D_mi lam_m),
-//                 J1 = d f#_KG(a, b) / d a (the flux is symmetric);
+//                 J1 = d f#(a, b) / d a of the symmetric two-point flux
+//                 (Kennedy-Gruber, or Chandrashekar's with its logarithmic
+//                 means differentiated on the branch the forward takes);
 //               * viscous volume term: Fvbar_d(m) = s_d sum_i D_im lam_i, then
 //                 the transpose of f_v,d(u, grad) -> (ubar, gbar);
 //               * each face node's numerical flux, which enters both sides'
@@ -23,9 +25,12 @@
 //   k_vjp_b : gbar (+ neighbour gbar at face nodes) -> qbar of q = (u, v, w, T)
 //             through the transposed BR1 lifting, then Ubar += (dq/dU)^T qbar.
 //
-// Non-smooth points: |u_d| and the max of the Lax-Friedrichs speed take the
-// derivative of the branch that is active (ties to the lower side L), as the
-// CPU oracle's reverse mode does.
+// The Roe dissipation's derivative with respect to the own face state is taken
+// in forward mode (five dual-number evaluations per face node).  Non-smooth
+// points: |u_d| and the max of the Lax-Friedrichs speed, and |lambda| and the
+// entropy correction's branch of the Roe flux, take the derivative of the
+// branch that is active (ties to the lower side L), as the CPU oracle's
+// reverse mode does.
 #include "dg_device.hpp"
 
 namespace dg {
@@ -104,11 +109,155 @@ __device__ inline void to_prim(const double s[5], const DevPhys& ph, double a[6]
   a[5] = P.e;
 }
 
+// ---- entropy-conserving / Roe pair ----
+
+// Logarithmic-mean factors of f = (x_a - x_b) / (x_a + x_b) (the forward
+// pair's switch: series for f^2 < 1e-4, atanh otherwise):
+//   G = f / atanh f (x_ln = (x_a + x_b) G / 2),  F = atanh f / f (1 / x_ln = 2 F / (x_a + x_b)),
+// with dG = dG/df and dF = dF/df.
+__device__ inline void ln_mean_factors(double f, double& G, double& dG, double& F, double& dF,
+                                       bool want_G) {
+  const double u = f * f;
+  if (u < 1e-4) {
+    G = 1.0 - u * (1.0 / 3.0 + u * (4.0 / 45.0 + u * (44.0 / 945.0)));
+    dG = -2.0 * f * (1.0 / 3.0 + u * (8.0 / 45.0 + u * (132.0 / 945.0)));
+    F = 1.0 + u * (1.0 / 3.0 + u * (0.2 + u * (1.0 / 7.0)));
+    dF = 2.0 * f * (1.0 / 3.0 + u * (0.4 + u * (3.0 / 7.0)));
+  } else {
+    const double t = atanh(f), r = f / (1.0 - u);
+    if (want_G) {
+      G = f / t;
+      dG = (t - r) / (t * t);
+    } else {
+      F = t / f;
+      dF = (r - t) / u;
+    }
+  }
+}
+
+// abar += (d f#_EC(a, b) / d a)^T mu for Chandrashekar's flux along d, a and b
+// = (rho, u, v, w, p, beta), beta = rho / (2 p); abar[5] is the cotangent of
+// beta (p enters the flux only through beta).  With um = {{u}},
+// q2m = {{|u|^2}}, F1 = rho_ln um_d, p^ = {{rho}} / (2 {{beta}}) and
+// kappa = 1 / (2 (gamma - 1)), mu . f# = F1 A + p^ Bp where
+//   A = mu_0 + mu_m . um + mu_4 (kappa / beta_ln - q2m / 2 + |um|^2),  Bp = mu_{1+d} + mu_4 um_d.
+template <int d>
+__device__ inline void ec_vjp(const double a[6], const double b[6], const double mu[5],
+                              double gm1, double abar[6]) {
+  const double sr = a[0] + b[0], sb = a[5] + b[5];
+  const double ir = 1.0 / sr, ib = 1.0 / sb;
+  double G, dG, F, dF, unused0, unused1;
+  ln_mean_factors((a[0] - b[0]) * ir, G, dG, unused0, unused1, true);
+  ln_mean_factors((a[5] - b[5]) * ib, unused0, unused1, F, dF, false);
+  const double rho_ln = 0.5 * sr * G;
+  const double ibl = 2.0 * ib * F;
+  const double p_hat = 0.5 * sr * ib;
+  const double um[3] = {0.5 * (a[1] + b[1]), 0.5 * (a[2] + b[2]), 0.5 * (a[3] + b[3])};
+  const double q2m = 0.5 * (a[1] * a[1] + a[2] * a[2] + a[3] * a[3] + b[1] * b[1] + b[2] * b[2] + b[3] * b[3]);
+  const double um2 = um[0] * um[0] + um[1] * um[1] + um[2] * um[2];
+  const double F1 = rho_ln * um[d];
+  const double kap = 0.5 / gm1;
+  const double A = mu[0] + mu[1] * um[0] + mu[2] * um[1] + mu[3] * um[2] +
+                   mu[4] * (kap * ibl - 0.5 * q2m + um2);
+  const double Bp = mu[1 + d] + mu[4] * um[d];
+  // d rho_ln / d rho_a = G / 2 + rho_b G' / sr;  d (1 / beta_ln) / d beta_a = -2 ib^2 F + 4 beta_b ib^3 F'
+  const double drl = 0.5 * G + b[0] * dG * ir;
+  const double dibl = ib * ib * (-2.0 * F + 4.0 * b[5] * ib * dF);
+  abar[0] += A * um[d] * drl + 0.5 * ib * Bp;
+  abar[5] += F1 * mu[4] * kap * dibl - 0.5 * sr * ib * ib * Bp;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double sk = F1 * (mu[1 + k] + 2.0 * mu[4] * um[k]);
+    if (k == d) sk += mu[4] * p_hat + A * rho_ln;
+    abar[1 + k] += 0.5 * sk - 0.5 * F1 * mu[4] * a[1 + k];
+  }
+}
+
+// Pb += the (rho, u, v, w, p) cotangent of Pbe, whose slot 5 is the cotangent
+// of beta = rho / (2 p) at the primitives a.
+__device__ inline void fold_beta(const double a[6], const double Pbe[6], double Pb[6]) {
+  const double ip = 1.0 / a[4];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) Pb[q] += Pbe[q];
+  Pb[0] += 0.5 * ip * Pbe[5];
+  Pb[4] -= a[5] * ip * Pbe[5];
+}
+
+}  // namespace
+
+// Forward-mode dual numbers v + t eps (eps^2 = 0) for the Roe dissipation's
+// derivatives; the operations the dissipation uses, found by argument-dependent
+// lookup from its template.
+namespace ad {
+struct Dual {
+  double v, t;
+  Dual() = default;
+  __device__ explicit constexpr Dual(double x, double dx = 0.0) : v(x), t(dx) {}
+};
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.t + b.t); }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.t - b.t); }
+__device__ inline Dual operator-(Dual a) { return Dual(-a.v, -a.t); }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.t * b.v + a.v * b.t); }
+__device__ inline Dual operator*(double s, Dual a) { return Dual(s * a.v, s * a.t); }
+__device__ inline Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return Dual(q, (a.t - q * b.t) / b.v);
+}
+__device__ inline Dual operator/(double s, Dual b) {
+  const double q = s / b.v;
+  return Dual(q, -q * b.t / b.v);
+}
+__device__ inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
+__device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+__device__ inline bool operator>(Dual a, double s) { return a.v > s; }
+__device__ inline Dual sqrt(Dual a) {
+  const double r = ::sqrt(a.v);
+  return Dual(r, 0.5 * a.t / r);
+}
+// |x| and max(x, y) take the branch the values select (ties to the first argument)
+__device__ inline Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
+__device__ inline Dual fmax(Dual a, Dual b) { return a.v >= b.v ? a : b; }
+}  // namespace ad
+
+namespace {
+
+// Ud += -(1/2) (d Roe(U_L, U_R) / d U_own)^T phi: one dual evaluation of the
+// dissipation per conservative component of the own state (own = L when
+// own_L), the neighbour state held fixed.
+template <int d>
+__device__ inline void roe_vjp(const double so[5], const double sn[5], bool own_L,
+                               const double phi[5], const DevPhys& ph, double Ud[5]) {
+  using ad::Dual;
+  const double irn = 1.0 / sn[0];
+  const double un = sn[1] * irn, vn = sn[2] * irn, wn = sn[3] * irn;
+  const double pn = ph.gm1 * (sn[4] - 0.5 * sn[0] * (un * un + vn * vn + wn * wn));
+  const Dual Pn[5] = {Dual(sn[0]), Dual(un), Dual(vn), Dual(wn), Dual(pn)};
+  const Dual En(sn[4]);
+#pragma unroll 1
+  for (int c = 0; c < 5; ++c) {
+    Dual s[5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) s[v] = Dual(so[v], v == c ? 1.0 : 0.0);
+    const Dual ir = 1.0 / s[0];
+    const Dual u = s[1] * ir, v = s[2] * ir, w = s[3] * ir;
+    const Dual Po[5] = {s[0], u, v, w, ph.gm1 * (s[4] - 0.5 * (s[0] * (u * u + v * v + w * w)))};
+    Dual D[5];
+    if (own_L)
+      roe_dissipation<d>(Po, s[4], Pn, En, ph.gamma, D);
+    else
+      roe_dissipation<d>(Pn, En, Po, s[4], ph.gamma, D);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) acc += phi[q] * D[q].t;
+    Ud[c] -= 0.5 * acc;
+  }
+}
+
 // Cotangents of one face node of the own element (o) in k_vjp_a: the state
 // cotangent Ud (the primitive map already applied), the cotangent Fvb of the
 // own normal viscous flux f_v,d, and om, the cotangent of the u . tau_d term
 // that a wall removes from the viscous flux.
-template <int d>
+template <int d, bool EC>
 __device__ inline void face_vjp(const double so[5], const double lo[5], const double sn[5],
                                 const double ln[5], bool wall, bool up, double s_o, double s_n,
                                 const DevPhys& ph, double inv_w, double Ud[5], double Fvb[4],
@@ -136,24 +285,34 @@ __device__ inline void face_vjp(const double so[5], const double lo[5], const do
     const double sc_n = -sc_o;
 #pragma unroll
     for (int v = 0; v < 5; ++v) phi[v] = psi[v] - sc_n * s_n * ln[v];
-    kg_vjp<d>(Po, Pn, phi, Pb);
-    if (!ph.central) {
-      const double co = fabs(Po[1 + d]) + sqrt(ph.gamma * Po[4] / Po[0]);
-      const double cn = fabs(Pn[1 + d]) + sqrt(ph.gamma * Pn[4] / Pn[0]);
-      // the own element is the lower side L of the face when the face is its upper one
-      const bool own_L = up;
-      const double lam = own_L ? (co >= cn ? co : cn) : (cn >= co ? cn : co);
-      const bool own_active = own_L ? (co >= cn) : (co > cn);
-      // F*_c contains -lam/2 (U_R - U_L)
-      const double dU = own_L ? 0.5 * lam : -0.5 * lam;
-      double lb = 0.0;
+    if constexpr (EC) {
+      // F*_c = f#_EC(U_L, U_R) - (1/2) Roe(U_L, U_R), the own element is L when up
+      const double Ae[6] = {Po[0], Po[1], Po[2], Po[3], Po[4], 0.5 * Po[0] / Po[4]};
+      const double Be[6] = {Pn[0], Pn[1], Pn[2], Pn[3], Pn[4], 0.5 * Pn[0] / Pn[4]};
+      double Pbe[6] = {0, 0, 0, 0, 0, 0};
+      ec_vjp<d>(Ae, Be, phi, ph.gm1, Pbe);
+      fold_beta(Ae, Pbe, Pb);
+      if (!ph.central) roe_vjp<d>(so, sn, up, phi, ph, Ud);
+    } else {
+      kg_vjp<d>(Po, Pn, phi, Pb);
+      if (!ph.central) {
+        const double co = fabs(Po[1 + d]) + sqrt(ph.gamma * Po[4] / Po[0]);
+        const double cn = fabs(Pn[1 + d]) + sqrt(ph.gamma * Pn[4] / Pn[0]);
+        // the own element is the lower side L of the face when the face is its upper one
+        const bool own_L = up;
+        const double lam = own_L ? (co >= cn ? co : cn) : (cn >= co ? cn : co);
+        const bool own_active = own_L ? (co >= cn) : (co > cn);
+        // F*_c contains -lam/2 (U_R - U_L)
+        const double dU = own_L ? 0.5 * lam : -0.5 * lam;
+        double lb = 0.0;
 #pragma unroll
-      for (int v = 0; v < 5; ++v) {
-        Ud[v] += dU * phi[v];
-        const double jump = own_L ? sn[v] - so[v] : so[v] - sn[v];
-        lb -= 0.5 * phi[v] * jump;
+        for (int v = 0; v < 5; ++v) {
+          Ud[v] += dU * phi[v];
+          const double jump = own_L ? sn[v] - so[v] : so[v] - sn[v];
+          lb -= 0.5 * phi[v] * jump;
+        }
+        if (own_active) speed_vjp<d>(Po, lb, ph, Pb);
       }
-      if (own_active) speed_vjp<d>(Po, lb, ph, Pb);
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) Fvb[c] -= 0.5 * phi[1 + c];
@@ -184,7 +343,7 @@ __device__ inline double nb_scale(const DevMesh& m, int ex, int ey, int ez, int 
 // bounded for four waves per SIMD: unrolled, each iteration's LDS operands
 // are hoisted and the kernel needs all 256 registers (two waves per SIMD,
 // 15 % slower at degree 5).
-template <int N>
+template <int N, bool EC>
 __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_vjp_a(const double* __restrict__ U,
                                                        const double* __restrict__ lam,
                                                        double* __restrict__ gbar,
@@ -224,6 +383,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     double s[5];
     load_state(U, stride, e * NN + node, s);
     to_prim(s, ph, own);
+    if (EC) own[5] = 0.5 * own[0] / own[4];  // beta in place of e
     load_state(lam, stride, e * NN + node, lo);
 #pragma unroll
     for (int q = 0; q < 6; ++q) sP[le][q][l] = own[q];
@@ -270,11 +430,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       }
       double Ud[5], Fvb[4], om;
       if (ft.d == 0)
-        face_vjp<0>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
+        face_vjp<0, EC>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
       else if (ft.d == 1)
-        face_vjp<1>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
+        face_vjp<1, EC>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
       else
-        face_vjp<2>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
+        face_vjp<2, EC>(so, fl, sn, ln, wall, ft.up, s_o, s_n, ph, basis.inv_w_end, Ud, Fvb, om);
 #pragma unroll
       for (int v = 0; v < 5; ++v) sFU[ft.le][ft.f][v][ft.ab] = Ud[v];
 #pragma unroll
@@ -345,7 +505,10 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       _Pragma("unroll") for (int q = 0; q < 6; ++q) b[q] = sP[le][q][lm];                      \
       _Pragma("unroll") for (int v = 0; v < 5; ++v) lmv[v] = sL[le][v][lm];                    \
       _Pragma("unroll") for (int v = 0; v < 5; ++v) mu5[v] = -2.0 * sd * (Dim * lo[v] + Dmi * lmv[v]); \
-      kg_vjp<D>(own, b, mu5, Pb);                                                              \
+      if constexpr (EC)                                                                        \
+        ec_vjp<D>(own, b, mu5, ph.gm1, Pb);                                                    \
+      else                                                                                     \
+        kg_vjp<D>(own, b, mu5, Pb);                                                            \
       _Pragma("unroll") for (int c = 0; c < 4; ++c) Fv[c] += sd * Dmi * lmv[1 + c];             \
     }                                                                                          \
     double omd = 0.0;                                                                          \
@@ -395,6 +558,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
     for (int d = 0; d < 3; ++d) st += gT[d] * g[9 + d];
     Tb = (1.5 / Tn - 1.0 / (Tn + ph.suth_S)) * st;
+  }
+  if (EC) {
+    // slot 5 holds the cotangent of beta = rho / (2 p)
+    const double Pbe[6] = {0, 0, 0, 0, 0, Pb[5]};
+    Pb[5] = 0.0;
+    fold_beta(own, Pbe, Pb);
   }
   double s[5];
   load_state(U, stride, idx, s);
@@ -524,8 +693,12 @@ template <int N>
 hipError_t vjp_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
                  const double* lam, double* gbar, double* ubar, double* out,
                  bool acc, double scale, double* cot, double cot_a, double cot_b, hipStream_t s) {
-  hipLaunchKernelGGL((k_vjp_a<N>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U, lam,
-                     gbar, ubar, m, p, b);
+  if (p.ec)
+    hipLaunchKernelGGL((k_vjp_a<N, true>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U,
+                       lam, gbar, ubar, m, p, b);
+  else
+    hipLaunchKernelGGL((k_vjp_a<N, false>), dim3(n_blocks<N>(m.nE)), dim3(Cfg<N>::BS), 0, s, U,
+                       lam, gbar, ubar, m, p, b);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   if (acc)

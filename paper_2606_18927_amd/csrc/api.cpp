@@ -263,8 +263,6 @@ dg_status need_adjoint(dg_ctx* c) {
   dg_status st = need_bound(c);
   if (st != DG_OK) return st;
   if (!c->adjoint_bound) return fail(c, DG_ESTATE, "workspace bound without the adjoint buffers");
-  if (c->phys.flux != DG_FLUX_KG_LLF)
-    return fail(c, DG_EUNSUPPORTED, "the adjoint is built for the Kennedy-Gruber / Lax-Friedrichs fluxes");
   if (c->wall_model) return fail(c, DG_EUNSUPPORTED, "the adjoint does not cover the wall model");
   if (c->curvilinear) return fail(c, DG_EUNSUPPORTED, "the adjoint is built for axis-aligned elements");
   return DG_OK;

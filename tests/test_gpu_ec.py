@@ -85,16 +85,12 @@ def test_ec_tgv_n3_rk_against_oracle():
 
 def test_ec_unsupported_combinations():
     need_gpu()
-    mesh, g, U = _case(3, (2, 2, 2), P3, seed=1)
+    mesh, g, _ = _case(3, (2, 2, 2), P3, seed=1)
     spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall)
     with pytest.raises(dgsem.DgsemError) as ei:
         dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, flux="ec_roe", precision="mixed")
     assert ei.value.status == dgsem.DG_EUNSUPPORTED
-    S = _solver(mesh, g, with_adjoint=True)
-    Ud = to_dev(U)
-    with pytest.raises(dgsem.DgsemError) as ei:
-        S.eval_rhs_vjp(Ud, Ud)
-    assert ei.value.status == dgsem.DG_EUNSUPPORTED
+    # (the adjoint covers this pair: tests/test_gpu_adjoint_ec.py)
 
 
 # --------------------------------------------------- full N=7, 32^3 workload
