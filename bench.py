@@ -328,35 +328,44 @@ def run_adjoint(steps: int, K: int):
     torch.cuda.synchronize()
     t_adj = a.elapsed_time(b)
     peak_extra = torch.cuda.max_memory_allocated() - base_mem
-    # kernel level: one right-hand side vs one vector-Jacobian product (FP64)
+    # kernel level: one right-hand side vs one vector-Jacobian product (FP64),
+    # for both flux pairs
     lam = torch.randn_like(Ud)
-    Sf = dgsem.solver_for(wl, with_adjoint=True, precision="fp64")
-    out = Sf.state_like()
-    for _ in range(2):
-        Sf.eval_rhs(Ud, out)
-        Sf.eval_rhs_vjp(Ud, lam, out)
-    reps = 5
-    a, b = ev()
-    a.record(Sf.stream)
-    for _ in range(reps):
-        Sf.eval_rhs(Ud, out)
-    b.record(Sf.stream)
-    c, d = ev()
-    c.record(Sf.stream)
-    for _ in range(reps):
-        Sf.eval_rhs_vjp(Ud, lam, out)
-    d.record(Sf.stream)
-    torch.cuda.synchronize()
-    t_rhs, t_vjp = a.elapsed_time(b) / reps, c.elapsed_time(d) / reps
+
+    def rhs_vs_vjp(flux):
+        Sf = dgsem.solver_for(wl, with_adjoint=True, precision="fp64", flux=flux)
+        out = Sf.state_like()
+        for _ in range(2):
+            Sf.eval_rhs(Ud, out)
+            Sf.eval_rhs_vjp(Ud, lam, out)
+        reps = 5
+        a, b = ev()
+        a.record(Sf.stream)
+        for _ in range(reps):
+            Sf.eval_rhs(Ud, out)
+        b.record(Sf.stream)
+        c, d = ev()
+        c.record(Sf.stream)
+        for _ in range(reps):
+            Sf.eval_rhs_vjp(Ud, lam, out)
+        d.record(Sf.stream)
+        Sf.sync()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps, c.elapsed_time(d) / reps
+
+    t_rhs, t_vjp = rhs_vs_vjp("kg_llf")
+    t_rhs_ec, t_vjp_ec = rhs_vs_vjp("ec_roe")
     dof = S.n_dof
     res = {"workload": wl.name, "dof": dof, "steps": steps, "checkpoint_every": K,
            "forward_precision": "mixed", "adjoint_precision": "fp64",
            "forward_ms": t_fwd, "forward_ns_per_dof_stage": t_fwd * 1e6 / (dof * steps * 5),
            "adjoint_total_ms": t_adj, "adjoint_forward_ratio": t_adj / t_fwd,
            "eval_rhs_fp64_ms": t_rhs, "eval_rhs_vjp_fp64_ms": t_vjp, "vjp_rhs_ratio": t_vjp / t_rhs,
+           "ec_roe": {"eval_rhs_fp64_ms": t_rhs_ec, "eval_rhs_vjp_fp64_ms": t_vjp_ec,
+                      "vjp_rhs_ratio": t_vjp_ec / t_rhs_ec},
            "workspace_gb": S.workspace_bytes / 1e9, "adjoint_extra_peak_gb": peak_extra / 1e9,
            "J": J.item()}
-    del S, Sf
+    del S
     torch.cuda.empty_cache()
     return res
 
@@ -432,7 +441,9 @@ def main():
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint(args.adjoint_steps, 25)
-        print(f"[bench] adjoint/forward {adjoint['adjoint_forward_ratio']:.2f}", file=sys.stderr, flush=True)
+        print(f"[bench] adjoint/forward {adjoint['adjoint_forward_ratio']:.2f}; vjp/rhs kg_llf "
+              f"{adjoint['vjp_rhs_ratio']:.2f}, ec_roe {adjoint['ec_roe']['vjp_rhs_ratio']:.2f}",
+              file=sys.stderr, flush=True)
     triad = triad_gbs()
     print(f"[bench] triad {triad:.0f} GB/s", file=sys.stderr, flush=True)
     cpu = None if args.no_cpu else cpu_baseline(wl)

@@ -25,8 +25,7 @@
 //   k_vjp_b : gbar (+ neighbour gbar at face nodes) -> qbar of q = (u, v, w, T)
 //             through the transposed BR1 lifting, then Ubar += (dq/dU)^T qbar.
 //
-// The Roe dissipation's derivative with respect to the own face state is taken
-// in forward mode (five dual-number evaluations per face node).  Non-smooth
+// The Roe dissipation's derivative is written out in reverse mode.  Non-smooth
 // points: |u_d| and the max of the Lax-Friedrichs speed, and |lambda| and the
 // entropy correction's branch of the Roe flux, take the derivative of the
 // branch that is active (ties to the lower side L), as the CPU oracle's
@@ -183,74 +182,158 @@ __device__ inline void fold_beta(const double a[6], const double Pbe[6], double 
   Pb[4] -= a[5] * ip * Pbe[5];
 }
 
-}  // namespace
-
-// Forward-mode dual numbers v + t eps (eps^2 = 0) for the Roe dissipation's
-// derivatives; the operations the dissipation uses, found by argument-dependent
-// lookup from its template.
-namespace ad {
-struct Dual {
-  double v, t;
-  Dual() = default;
-  __device__ explicit constexpr Dual(double x, double dx = 0.0) : v(x), t(dx) {}
-};
-__device__ inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.t + b.t); }
-__device__ inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.t - b.t); }
-__device__ inline Dual operator-(Dual a) { return Dual(-a.v, -a.t); }
-__device__ inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.t * b.v + a.v * b.t); }
-__device__ inline Dual operator*(double s, Dual a) { return Dual(s * a.v, s * a.t); }
-__device__ inline Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
-  return Dual(q, (a.t - q * b.t) / b.v);
+// lam_bar, lamL_bar, lamR_bar += gb d hh(lam, lamL, lamR): Harten-Hyman |lambda|
+// (the branch and the max that the values select, ties to the first argument).
+__device__ inline void hh_vjp(double lam, double lamL, double lamR, double gb, double& lb,
+                              double& lLb, double& lRb) {
+  const double d1 = lam - lamL, d2 = lamR - lam;
+  const bool first = d1 >= d2;
+  const double delta = first ? d1 : d2;
+  if (delta > 0.0 && fabs(lam) < delta) {
+    const double bd = gb * (delta * delta - lam * lam) / (2.0 * delta * delta);
+    lb += gb * lam / delta + (first ? bd : -bd);
+    if (first)
+      lLb -= bd;
+    else
+      lRb += bd;
+  } else {
+    lb += lam > 0.0 ? gb : (lam < 0.0 ? -gb : 0.0);
+  }
 }
-__device__ inline Dual operator/(double s, Dual b) {
-  const double q = s / b.v;
-  return Dual(q, -q * b.t / b.v);
-}
-__device__ inline Dual& operator+=(Dual& a, Dual b) { return a = a + b; }
-__device__ inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
-__device__ inline bool operator>(Dual a, double s) { return a.v > s; }
-__device__ inline Dual sqrt(Dual a) {
-  const double r = ::sqrt(a.v);
-  return Dual(r, 0.5 * a.t / r);
-}
-// |x| and max(x, y) take the branch the values select (ties to the first argument)
-__device__ inline Dual fabs(Dual a) { return a.v < 0.0 ? -a : a; }
-__device__ inline Dual fmax(Dual a, Dual b) { return a.v >= b.v ? a : b; }
-}  // namespace ad
 
-namespace {
-
-// Ud += -(1/2) (d Roe(U_L, U_R) / d U_own)^T phi: one dual evaluation of the
-// dissipation per conservative component of the own state (own = L when
-// own_L), the neighbour state held fixed.
+// Pb += -(1/2) (d Roe(U_L, U_R) / d P_own)^T phi in the own primitives
+// (rho, u, v, w, p, e): reverse mode of the Roe dissipation (the forward
+// quantities of that function, then their cotangents in reverse order), own =
+// L when own_L; E = rho e carries the total-energy cotangent into rho and e.
 template <int d>
 __device__ inline void roe_vjp(const double so[5], const double sn[5], bool own_L,
-                               const double phi[5], const DevPhys& ph, double Ud[5]) {
-  using ad::Dual;
-  const double irn = 1.0 / sn[0];
-  const double un = sn[1] * irn, vn = sn[2] * irn, wn = sn[3] * irn;
-  const double pn = ph.gm1 * (sn[4] - 0.5 * sn[0] * (un * un + vn * vn + wn * wn));
-  const Dual Pn[5] = {Dual(sn[0]), Dual(un), Dual(vn), Dual(wn), Dual(pn)};
-  const Dual En(sn[4]);
-#pragma unroll 1
-  for (int c = 0; c < 5; ++c) {
-    Dual s[5];
+                               const double phi[5], const DevPhys& ph, double Pb[6]) {
+  const double* sL = own_L ? so : sn;
+  const double* sR = own_L ? sn : so;
+  double L[5], R[5];
+  {
+    const double il = 1.0 / sL[0], ir = 1.0 / sR[0];
+    L[0] = sL[0];
+    R[0] = sR[0];
 #pragma unroll
-    for (int v = 0; v < 5; ++v) s[v] = Dual(so[v], v == c ? 1.0 : 0.0);
-    const Dual ir = 1.0 / s[0];
-    const Dual u = s[1] * ir, v = s[2] * ir, w = s[3] * ir;
-    const Dual Po[5] = {s[0], u, v, w, ph.gm1 * (s[4] - 0.5 * (s[0] * (u * u + v * v + w * w)))};
-    Dual D[5];
-    if (own_L)
-      roe_dissipation<d>(Po, s[4], Pn, En, ph.gamma, D);
-    else
-      roe_dissipation<d>(Pn, En, Po, s[4], ph.gamma, D);
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) acc += phi[q] * D[q].t;
-    Ud[c] -= 0.5 * acc;
+    for (int c = 0; c < 3; ++c) {
+      L[1 + c] = sL[1 + c] * il;
+      R[1 + c] = sR[1 + c] * ir;
+    }
+    L[4] = ph.gm1 * (sL[4] - 0.5 * sL[0] * (L[1] * L[1] + L[2] * L[2] + L[3] * L[3]));
+    R[4] = ph.gm1 * (sR[4] - 0.5 * sR[0] * (R[1] * R[1] + R[2] * R[2] + R[3] * R[3]));
   }
+  const double EL = sL[4], ER = sR[4];
+  // forward
+  const double sl = sqrt(L[0]), sr = sqrt(R[0]);
+  const double isum = 1.0 / (sl + sr);
+  const double wl = sl * isum, wr = sr * isum;
+  double ut[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ut[c] = wl * L[1 + c] + wr * R[1 + c];
+  const double hL = (EL + L[4]) / L[0], hR = (ER + R[4]) / R[0];
+  const double H = wl * hL + wr * hR;
+  const double q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const double a2 = ph.gm1 * (H - 0.5 * q2);
+  const double a = sqrt(a2);
+  const double rho = sl * sr;
+  const double un = ut[d];
+  const double dp = R[4] - L[4];
+  const double dud = R[1 + d] - L[1 + d];
+  const double i2a2 = 0.5 / a2;
+  const double al1 = (dp - rho * a * dud) * i2a2, al5 = (dp + rho * a * dud) * i2a2;
+  const double al2 = (R[0] - L[0]) - dp / a2;
+  const double cl = sqrt(ph.gamma * L[4] / L[0]), cr = sqrt(ph.gamma * R[4] / R[0]);
+  const double l1 = hh_abs(un - a, L[1 + d] - cl, R[1 + d] - cr);
+  const double l5 = hh_abs(un + a, L[1 + d] + cl, R[1 + d] + cr);
+  const double l2 = fabs(un);
+  const double t1 = l1 * al1, t5 = l5 * al5, t2 = l2 * al2, ts = l2 * rho;
+  const double T = t1 + t2 + t5;
+  // reverse, with the cotangent -phi/2 of the dissipation
+  double g[5];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) g[v] = -0.5 * phi[v];
+  double Lb[5] = {0, 0, 0, 0, 0}, Rb[5] = {0, 0, 0, 0, 0};
+  double Tb = g[0], tsb = 0.0, udtb = g[4] * ts, utb[3], udt = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double sh = c == d ? 0.0 : R[1 + c] - L[1 + c];
+    udt += ut[c] * sh;
+    Tb += g[1 + c] * ut[c];
+    utb[c] = g[1 + c] * T + udtb * sh;
+    tsb += g[1 + c] * sh;
+    // the shear jump (c != d): ts d(D_{1+c})/d du_c + ut_c d(D_4)/d du_c
+    const double dub = c == d ? 0.0 : g[1 + c] * ts + udtb * ut[c];
+    Rb[1 + c] += dub;
+    Lb[1 + c] -= dub;
+  }
+  double t5b = g[1 + d] * a + g[4] * (H + un * a) + Tb;
+  double t1b = -g[1 + d] * a + g[4] * (H - un * a) + Tb;
+  const double t2b = g[4] * 0.5 * q2 + Tb;
+  tsb += g[4] * udt;
+  double ab = (g[1 + d] + g[4] * un) * (t5 - t1);
+  double Hb = g[4] * (t1 + t5);
+  double unb = g[4] * a * (t5 - t1);
+  double q2b = g[4] * 0.5 * t2;
+  const double l2b = tsb * rho + t2b * al2;
+  double rhob = tsb * l2;
+  const double al2b = t2b * l2, al5b = t5b * l5, al1b = t1b * l1;
+  unb += un > 0.0 ? l2b : (un < 0.0 ? -l2b : 0.0);
+  double b5 = 0.0, bL5 = 0.0, bR5 = 0.0, b1 = 0.0, bL1 = 0.0, bR1 = 0.0;
+  hh_vjp(un + a, L[1 + d] + cl, R[1 + d] + cr, t5b * al5, b5, bL5, bR5);
+  hh_vjp(un - a, L[1 + d] - cl, R[1 + d] - cr, t1b * al1, b1, bL1, bR1);
+  unb += b5 + b1;
+  ab += b5 - b1;
+  Lb[1 + d] += bL5 + bL1;
+  Rb[1 + d] += bR5 + bR1;
+  const double clb = bL5 - bL1, crb = bR5 - bR1;
+  Lb[4] += clb * cl / (2.0 * L[4]);
+  Lb[0] -= clb * cl / (2.0 * L[0]);
+  Rb[4] += crb * cr / (2.0 * R[4]);
+  Rb[0] -= crb * cr / (2.0 * R[0]);
+  Rb[0] += al2b;
+  Lb[0] -= al2b;
+  const double dpb = -al2b / a2 + (al1b + al5b) * i2a2;
+  double a2b = al2b * dp / (a2 * a2) - (al1b * al1 + al5b * al5) / a2;
+  const double dal = (al5b - al1b) * i2a2;
+  rhob += dal * a * dud;
+  ab += dal * rho * dud;
+  const double dudb = dal * rho * a;
+  Rb[1 + d] += dudb;
+  Lb[1 + d] -= dudb;
+  Rb[4] += dpb;
+  Lb[4] -= dpb;
+  utb[d] += unb;
+  double slb = rhob * sr, srb = rhob * sl;
+  a2b += ab / (2.0 * a);
+  Hb += a2b * ph.gm1;
+  q2b -= 0.5 * a2b * ph.gm1;
+  double wlb = Hb * hL, wrb = Hb * hR;
+  const double hLb = Hb * wl, hRb = Hb * wr;
+  const double ELb = hLb / L[0], ERb = hRb / R[0];
+  Lb[4] += ELb;
+  Lb[0] -= ELb * hL;
+  Rb[4] += ERb;
+  Rb[0] -= ERb * hR;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double u_b = utb[c] + 2.0 * q2b * ut[c];
+    wlb += u_b * L[1 + c];
+    wrb += u_b * R[1 + c];
+    Lb[1 + c] += u_b * wl;
+    Rb[1 + c] += u_b * wr;
+  }
+  slb += (wlb - wrb) * sr * isum * isum;
+  srb += (wrb - wlb) * sl * isum * isum;
+  Lb[0] += slb / (2.0 * sl);
+  Rb[0] += srb / (2.0 * sr);
+  // the own side: (rho, u, v, w, p) and E = rho e
+  const double* Xb = own_L ? Lb : Rb;
+  const double Eb = own_L ? ELb : ERb;
+#pragma unroll
+  for (int q = 0; q < 5; ++q) Pb[q] += Xb[q];
+  Pb[0] += Eb * so[4] / so[0];
+  Pb[5] += Eb * so[0];
 }
 
 // Cotangents of one face node of the own element (o) in k_vjp_a: the state
@@ -292,7 +375,7 @@ __device__ inline void face_vjp(const double so[5], const double lo[5], const do
       double Pbe[6] = {0, 0, 0, 0, 0, 0};
       ec_vjp<d>(Ae, Be, phi, ph.gm1, Pbe);
       fold_beta(Ae, Pbe, Pb);
-      if (!ph.central) roe_vjp<d>(so, sn, up, phi, ph, Ud);
+      if (!ph.central) roe_vjp<d>(so, sn, up, phi, ph, Pb);
     } else {
       kg_vjp<d>(Po, Pn, phi, Pb);
       if (!ph.central) {

@@ -217,59 +217,10 @@ __device__ inline void ec_means(double ra, double rb, double ba, double bb, doub
 // |lambda| with Harten's entropy correction in the Harten-Hyman form:
 // (lambda^2 + delta^2) / (2 delta) where |lambda| < delta,
 // delta = max(0, lambda - lambda_L, lambda_R - lambda).
-template <typename T>
-__device__ inline T hh_abs(T lam, T lam_L, T lam_R) {
-  T delta = fmax(lam - lam_L, lam_R - lam);
-  delta = delta > 0.0 ? delta : T(0.0);
+__device__ inline double hh_abs(double lam, double lam_L, double lam_R) {
+  double delta = fmax(lam - lam_L, lam_R - lam);
+  delta = delta > 0.0 ? delta : 0.0;
   return fabs(lam) < delta ? (lam * lam + delta * delta) / (2.0 * delta) : fabs(lam);
-}
-
-// Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with normal e_d
-// (L = lower side, R = upper side; primitives (rho, u, v, w, p) and total
-// energies E), linearised at the Roe average: sqrt(rho)-weighted u and
-// H = (E + p) / rho, rho~ = sqrt(rho_L rho_R), a~^2 = (gamma - 1)(H~ - |u~|^2 / 2).
-// Waves: acoustic u~_d -+ a~, alpha = ([[p]] -+ rho~ a~ [[u_d]]) / (2 a~^2),
-// r = (1, u~ -+ a~ e_d, H~ -+ u~_d a~) (eigenvalues with the correction above);
-// entropy u~_d, alpha = [[rho]] - [[p]] / a~^2, r = (1, u~, |u~|^2 / 2); shear
-// u~_d with rho~ (0, [[u_t]], u~ . [[u_t]]).
-// T is double, or a forward-mode dual number (the adjoint's face derivatives).
-template <int d, typename T>
-__device__ inline void roe_dissipation(const T L[5], T EL, const T R[5], T ER, double gamma,
-                                       T D[5]) {
-  const T sl = sqrt(L[0]), sr = sqrt(R[0]);
-  const T isum = 1.0 / (sl + sr);
-  const T wl = sl * isum, wr = sr * isum;
-  T ut[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) ut[c] = wl * L[1 + c] + wr * R[1 + c];
-  const T H = wl * (EL + L[4]) / L[0] + wr * (ER + R[4]) / R[0];
-  const T q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
-  const T a2 = (gamma - 1.0) * (H - 0.5 * q2);
-  const T a = sqrt(a2);
-  const T rho = sl * sr;
-  const T un = ut[d];
-  const T dp = R[4] - L[4];
-  T du[3];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) du[c] = R[1 + c] - L[1 + c];
-  const T al1 = (dp - rho * a * du[d]) / (2.0 * a2);
-  const T al5 = (dp + rho * a * du[d]) / (2.0 * a2);
-  const T al2 = (R[0] - L[0]) - dp / a2;
-  const T cl = sqrt(gamma * L[4] / L[0]), cr = sqrt(gamma * R[4] / R[0]);
-  const T l1 = hh_abs(un - a, L[1 + d] - cl, R[1 + d] - cr);
-  const T l5 = hh_abs(un + a, L[1 + d] + cl, R[1 + d] + cr);
-  const T l2 = fabs(un);
-  const T t1 = l1 * al1, t5 = l5 * al5, t2 = l2 * al2, ts = l2 * rho;
-  T udt = T(0.0);
-  D[0] = t1 + t2 + t5;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const T sh = c == d ? T(0.0) : du[c];
-    udt += ut[c] * sh;
-    D[1 + c] = t1 * ut[c] + t2 * ut[c] + t5 * ut[c] + ts * sh;
-  }
-  D[1 + d] += (t5 - t1) * a;
-  D[4] = t1 * (H - un * a) + t2 * (0.5 * q2) + t5 * (H + un * a) + ts * udt;
 }
 
 // Kennedy-Gruber two-point flux along d of states a, b = (rho, u, v, w, p, e).

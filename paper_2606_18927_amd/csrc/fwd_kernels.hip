@@ -583,6 +583,53 @@ __device__ inline void volume_sweep_ec(const double2 (&own)[3], int i, int j, in
   }
 }
 
+// Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with normal e_d
+// (L = lower side, R = upper side; primitives (rho, u, v, w, p) and total
+// energies E), linearised at the Roe average: sqrt(rho)-weighted u and
+// H = (E + p) / rho, rho~ = sqrt(rho_L rho_R), a~^2 = (gamma - 1)(H~ - |u~|^2 / 2).
+// Waves: acoustic u~_d -+ a~, alpha = ([[p]] -+ rho~ a~ [[u_d]]) / (2 a~^2),
+// r = (1, u~ -+ a~ e_d, H~ -+ u~_d a~) (eigenvalues with the correction above);
+// entropy u~_d, alpha = [[rho]] - [[p]] / a~^2, r = (1, u~, |u~|^2 / 2); shear
+// u~_d with rho~ (0, [[u_t]], u~ . [[u_t]]).
+template <int d>
+__device__ inline void roe_dissipation(const double L[5], double EL, const double R[5], double ER,
+                                       double gamma, double D[5]) {
+  const double sl = sqrt(L[0]), sr = sqrt(R[0]);
+  const double isum = 1.0 / (sl + sr);
+  const double wl = sl * isum, wr = sr * isum;
+  double ut[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) ut[c] = wl * L[1 + c] + wr * R[1 + c];
+  const double H = wl * (EL + L[4]) / L[0] + wr * (ER + R[4]) / R[0];
+  const double q2 = ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2];
+  const double a2 = (gamma - 1.0) * (H - 0.5 * q2);
+  const double a = sqrt(a2);
+  const double rho = sl * sr;
+  const double un = ut[d];
+  const double dp = R[4] - L[4];
+  double du[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) du[c] = R[1 + c] - L[1 + c];
+  const double al1 = (dp - rho * a * du[d]) / (2.0 * a2);
+  const double al5 = (dp + rho * a * du[d]) / (2.0 * a2);
+  const double al2 = (R[0] - L[0]) - dp / a2;
+  const double cl = sqrt(gamma * L[4] / L[0]), cr = sqrt(gamma * R[4] / R[0]);
+  const double l1 = hh_abs(un - a, L[1 + d] - cl, R[1 + d] - cr);
+  const double l5 = hh_abs(un + a, L[1 + d] + cl, R[1 + d] + cr);
+  const double l2 = fabs(un);
+  const double t1 = l1 * al1, t5 = l5 * al5, t2 = l2 * al2, ts = l2 * rho;
+  double udt = 0.0;
+  D[0] = t1 + t2 + t5;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const double sh = c == d ? 0.0 : du[c];
+    udt += ut[c] * sh;
+    D[1 + c] = t1 * ut[c] + t2 * ut[c] + t5 * ut[c] + ts * sh;
+  }
+  D[1 + d] += (t5 - t1) * a;
+  D[4] = t1 * (H - un * a) + t2 * (0.5 * q2) + t5 * (H + un * a) + ts * udt;
+}
+
 // Surface correction of one face task with the entropy-conserving / Roe pair
 // (FP64): ((F*_c - F*_v) - (f_c - f_v)(own)) (+-1/w_end),
 // F*_c = f#_EC(U_L, U_R) - (1/2) Roe dissipation.  A = own (rho, u, v, w, p,
