@@ -406,6 +406,12 @@ def main():
               "face_kernel_ms": r["face_kernel_ms"], "step_alg_gbs": r["step_alg_gbs"],
               "step_frac": r["step_alg_gbs"] / HBM_PEAK_GBS}
         print(f"[bench] ec_roe {ec['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
+        if not args.no_mixed:
+            rm, _ = run_precision(wl_ec, U, dt, "mixed", args.steps, args.warmup)
+            ec["mixed"] = {k: rm[k] for k in ("ns_per_dof_stage", "ms_per_step", "rk_kernel_ms",
+                                              "face_kernel_ms", "step_alg_gbs")}
+            print(f"[bench] ec_roe mixed {rm['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
+                  flush=True)
     suth = wall = None
     if not args.no_physics and wl.name == "tgv_n7_32x32x32":
         wl_s = workloads.WORKLOADS["tgv_n7_32x32x32_sutherland"]

@@ -63,8 +63,10 @@ typedef enum {
 #define DG_FLUX_EC_ROE 1  /* the paper's production pair (Sec. 4): Chandrashekar's
                              entropy-conserving volume flux; Roe surface flux with
                              Harten's entropy correction (Harten-Hyman form), its
-                             central part the Chandrashekar flux.  DG_FP64 only; the
-                             adjoint covers it                                         */
+                             central part the Chandrashekar flux.  DG_FP64, or
+                             DG_MIXED (the volume flux in FP32 relative to each
+                             element's reference state; DG_MIXED_NOREF gets
+                             DG_EUNSUPPORTED); the adjoint covers it                   */
 
 /* Viscosity laws (dg_physics.viscosity). */
 #define DG_VISC_CONSTANT 0    /* mu constant                                              */

@@ -311,7 +311,7 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
       phys->precision != DG_MIXED_NOREF)
     return DG_EINVAL;
   if (phys->flux != DG_FLUX_KG_LLF && phys->flux != DG_FLUX_EC_ROE) return DG_EINVAL;
-  if (phys->flux == DG_FLUX_EC_ROE && phys->precision != DG_FP64) return DG_EUNSUPPORTED;
+  if (phys->flux == DG_FLUX_EC_ROE && phys->precision == DG_MIXED_NOREF) return DG_EUNSUPPORTED;
   if (phys->viscosity != DG_VISC_CONSTANT && phys->viscosity != DG_VISC_SUTHERLAND) return DG_EINVAL;
   if (phys->viscosity == DG_VISC_SUTHERLAND) {
     if (!(phys->T_ref > 0.0) || !(phys->S >= 0.0) || !std::isfinite(phys->T_ref) || !std::isfinite(phys->S))

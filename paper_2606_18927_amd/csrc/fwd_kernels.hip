@@ -583,6 +583,72 @@ __device__ inline void volume_sweep_ec(const double2 (&own)[3], int i, int j, in
   }
 }
 
+// Line sums of direction d with the entropy-conserving flux in FP32 (mixed
+// precision), relative to the element's reference state (p_ref, beta_ref):
+// own, sp = (rho, u), (v, w), (beta - beta_ref, |u|^2), (pi, 0) with
+// pi = rho (p - p_ref) / p = rho - 2 p_ref beta.  Then, with sb = beta_a + beta_b,
+//   p^ - p_ref = (pi_a + pi_b) / (2 sb),
+//   1 / beta_ln - 1 / beta_ref = (2 (F - 1) - (dbeta_a + dbeta_b) / beta_ref) / sb,
+// F = atanh f / f of the beta pair (its series less the leading 1 below
+// f^2 = 1e-2, where the dropped term is below 2e-10), so no FP32 difference
+// of O(p_ref) terms is formed.  ac = sum_m D_im (f#_EC - (0, p_ref e_d,
+// F1 e_ref + p_ref {{u_d}})), du = sum_m D_im {{u_d}}, e_ref = p_ref / ((gamma - 1) rho_ref)
+// = kappa / beta_ref; the reference parts are added back in FP64 (the
+// pressure part vanishes: the rows of D sum to zero).
+template <int N, int d, bool VISC>
+__device__ inline void volume_sweep_ec_mixed(const float2 (&own)[4], int i, int j, int k,
+                                             const float* sD, const float2 (*sp)[GeoR<N>::EB],
+                                             const float2 (*sfv)[GeoR<N>::EB], float kap,
+                                             float beta_ref, float ibr, float ac[5], float av[4],
+                                             float& du) {
+  using Gm = GeoR<N>;
+  constexpr int NP = Gm::NP;
+  const int idx = d == 0 ? i : (d == 1 ? j : k);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) ac[v] = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) av[c] = 0.0f;
+  du = 0.0f;
+#pragma unroll 2
+  for (int m = 0; m < NP; ++m) {
+    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
+    const float Dim = sD[idx * Gm::DS + m];
+    const float2 b0 = sp[0][lm], b1 = sp[1][lm], b2 = sp[2][lm], b3 = sp[3][lm];
+    const float sr = own[0].x + b0.x, sdb = own[2].x + b2.x;
+    const float sb = 2.0f * beta_ref + sdb;
+    const float ir = __builtin_amdgcn_rcpf(sr), ib = __builtin_amdgcn_rcpf(sb);
+    const float fr = (own[0].x - b0.x) * ir, fb = (own[2].x - b2.x) * ib;
+    const float ur = fr * fr, ub = fb * fb;
+    float G = 1.0f - ur * (1.0f / 3.0f + ur * (4.0f / 45.0f + ur * (44.0f / 945.0f)));
+    float Fs = ub * (1.0f / 3.0f + ub * (0.2f + ub * (1.0f / 7.0f)));
+    if (ur >= 1e-2f) G = fr / atanhf(fr);
+    if (ub >= 1e-2f) Fs = atanhf(fb) / fb - 1.0f;
+    const float um = 0.5f * (own[0].y + b0.y), vm = 0.5f * (own[1].x + b1.x),
+                wm = 0.5f * (own[1].y + b1.y);
+    const float ud = d == 0 ? um : (d == 1 ? vm : wm);
+    const float F1 = 0.5f * sr * G * ud;
+    const float dp = 0.5f * (own[3].x + b3.x) * ib;
+    const float dib = (2.0f * Fs - sdb * ibr) * ib;
+    const float q2m = 0.5f * (own[2].y + b2.y);
+    const float X = kap * dib - 0.5f * q2m + (um * um + vm * vm + wm * wm);
+    const float s = Dim * F1;
+    ac[0] += s;
+    ac[1] += s * um;
+    ac[2] += s * vm;
+    ac[3] += s * wm;
+    ac[1 + d] += Dim * dp;
+    ac[4] += s * X + Dim * dp * ud;
+    du += Dim * ud;
+    if (VISC) {
+      const float2 f01 = sfv[0][lm], f23 = sfv[1][lm];
+      av[0] += Dim * f01.x;
+      av[1] += Dim * f01.y;
+      av[2] += Dim * f23.x;
+      av[3] += Dim * f23.y;
+    }
+  }
+}
+
 // Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with normal e_d
 // (L = lower side, R = upper side; primitives (rho, u, v, w, p) and total
 // energies E), linearised at the Roe average: sqrt(rho)-weighted u and
@@ -698,11 +764,13 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   constexpr int EPB = Cfg<N>::EPB, BS = Cfg<N>::BS;
   constexpr bool MIXED = sizeof(R) == 4;
   using V2 = typename V2T<R>::type;
-  static_assert(!EC || !MIXED, "the entropy-conserving pair is FP64 only");
+  // entries of sp per node: 4 for the mixed-precision entropy-conserving pair
+  constexpr int NSP = EC && MIXED ? 4 : 3;
   __shared__ R sD[NP * Gm::DS];
   // halves of (rho, u), (v, w), (p - p_ref, e - e_ref); with EC the full values
-  // (rho, u), (v, w), (beta, |u|^2)
-  __shared__ V2 sp[EPB][3][EB];
+  // (rho, u), (v, w), (beta, |u|^2), in mixed precision (rho, u), (v, w),
+  // (beta - beta_ref, |u|^2), (rho (p - p_ref) / p, 0)
+  __shared__ V2 sp[EPB][NSP][EB];
   __shared__ V2 sfv[EPB][2][EB];    // f_v,d of the current direction; T - T_ref in P1-P2
   // sX: lifting corrections (P1-P2, as ssq), own f_v,d of the face nodes in
   // components 0..3 (P3-P4), surface corrections (P4-P5).  In P4 every face
@@ -777,10 +845,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   }
 
   // ---- P1: node lanes --------------------------------------------------
-  V2 own[3];
-  own[0].x = own[0].y = own[1].x = own[1].y = own[2].x = own[2].y = R(0);
+  V2 own[NSP];
+#pragma unroll
+  for (int q = 0; q < NSP; ++q) own[q].x = own[q].y = R(0);
   R uo = R(0), vo = R(0), wo = R(0);  // own velocity (full values)
-  double p_ref = 0.0, e_ref = 0.0;
+  double p_ref = 0.0, e_ref = 0.0, beta_ref = 0.0;
   int ex = ex0, ey = ey0, ez = ez0;
   R* sT = reinterpret_cast<R*>(&sfv[le][0][0]);
   if (active) {
@@ -792,7 +861,19 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     uo = static_cast<R>(P.u);
     vo = static_cast<R>(P.v);
     wo = static_cast<R>(P.w);
-    if (EC) {
+    if (EC && MIXED) {
+      // reference: beta_ref = rho_ref / (2 p_ref); e_ref becomes the internal
+      // energy p_ref / ((gamma - 1) rho_ref) = kappa / beta_ref
+      beta_ref = 0.5 * s0[0] / p_ref;
+      e_ref = p_ref / (ph.gm1 * s0[0]);
+      own[0].x = static_cast<R>(P.rho);
+      own[0].y = static_cast<R>(P.u);
+      own[1].x = static_cast<R>(P.v);
+      own[1].y = static_cast<R>(P.w);
+      own[2].x = static_cast<R>(0.5 * P.rho / P.p - beta_ref);
+      own[2].y = static_cast<R>(P.u * P.u + P.v * P.v + P.w * P.w);
+      own[NSP - 1].x = static_cast<R>(P.rho * (P.p - p_ref) / P.p);
+    } else if (EC) {
       own[0].x = P.rho;
       own[0].y = P.u;
       own[1].x = P.v;
@@ -808,7 +889,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       own[2].y = static_cast<R>(0.5 * (P.e - e_ref));
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) sp[le][q][l] = own[q];
+    for (int q = 0; q < NSP; ++q) sp[le][q][l] = own[q];
     if (VISC) sT[l] = static_cast<R>(P.T - T_ref);
   }
   if (tid < NP * NP) sD[(tid / NP) * Gm::DS + tid % NP] = static_cast<R>(dval);
@@ -879,7 +960,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     __syncthreads();                                                                        \
     if (active) {                                                                           \
       R ac[5], av[4], du = R(0);                                                            \
-      if constexpr (EC)                                                                     \
+      if constexpr (EC && MIXED)                                                            \
+        volume_sweep_ec_mixed<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le],                \
+                                          static_cast<float>(0.5 / ph.gm1),                \
+                                          static_cast<float>(beta_ref),                    \
+                                          static_cast<float>(1.0 / beta_ref), ac, av, du); \
+      else if constexpr (EC)                                                                \
         volume_sweep_ec<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le], ph.gm1, ac, av);     \
       else                                                                                  \
         volume_sweep<N, R, D, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sfv[le], ac, av, du); \
@@ -926,6 +1012,10 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int v = 0; v < 5; ++v) so[v] = sO[ft.le][ft.f][v][ft.ab];
       const Prim P = primitives(so, ph);
       A[0] = P.rho; A[1] = P.u; A[2] = P.v; A[3] = P.w; A[4] = P.p; A[5] = P.e;
+      if (EC) {
+        A[5] = 0.5 * P.rho / P.p;
+        q2o = P.u * P.u + P.v * P.v + P.w * P.w;
+      }
     } else if (EC) {
       // (rho, u, v, w, beta, |u|^2) from sp; p and E recovered from them
       const int lo = Gm::lds(ft.oi, ft.oj, ft.ok);
@@ -1055,7 +1145,14 @@ hipError_t rhs_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const do
       return hipGetLastError();
     }
   } else {
-    if (p.ec) return hipErrorInvalidValue;  // rejected at init: FP64 only
+    if (p.ec) {
+      if (!p.mixed_ref) return hipErrorInvalidValue;  // rejected at init: needs the reference state
+      if (p.viscous)
+        launch_k_rhs<N, R, RK, true, true>(m, p, b, U, ffv, out, U_out, st, status, s);
+      else
+        launch_k_rhs<N, R, RK, false, true>(m, p, b, U, ffv, out, U_out, st, status, s);
+      return hipGetLastError();
+    }
   }
   if (p.viscous)
     launch_k_rhs<N, R, RK, true, false>(m, p, b, U, ffv, out, U_out, st, status, s);

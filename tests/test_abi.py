@@ -85,12 +85,14 @@ def test_init_mesh_validation_errors(L):
     L.dg_free(ctx)
     d, keep = _desc(N=4)
     assert _init(L, d, _phys())[0] == dgsem.DG_EUNSUPPORTED
-    # flux choice: the entropy-conserving / Roe pair is FP64 only; unknown values are rejected
+    # flux choice: the entropy-conserving / Roe pair in FP64 and mixed precision
+    # (not without the reference state); unknown values are rejected
     d, keep = _desc()
-    st, ctx = _init(L, d, _phys(flux=1))
-    assert st == dgsem.DG_OK
-    L.dg_free(ctx)
-    assert _init(L, d, _phys(flux=1, precision=1))[0] == dgsem.DG_EUNSUPPORTED
+    for prec in (0, 1):
+        st, ctx = _init(L, d, _phys(flux=1, precision=prec))
+        assert st == dgsem.DG_OK
+        L.dg_free(ctx)
+    assert _init(L, d, _phys(flux=1, precision=2))[0] == dgsem.DG_EUNSUPPORTED
     assert _init(L, d, _phys(flux=2))[0] == dgsem.DG_EINVAL
     # viscosity law: Sutherland's needs T_ref > 0 and S >= 0, and is FP64 only
     st, ctx = _init(L, d, _phys(viscosity=1, T_ref=1.0, S=0.38))

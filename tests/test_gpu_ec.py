@@ -88,7 +88,7 @@ def test_ec_unsupported_combinations():
     mesh, g, _ = _case(3, (2, 2, 2), P3, seed=1)
     spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall)
     with pytest.raises(dgsem.DgsemError) as ei:
-        dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, flux="ec_roe", precision="mixed")
+        dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr, flux="ec_roe", precision="mixed_noref")
     assert ei.value.status == dgsem.DG_EUNSUPPORTED
     # (the adjoint covers this pair: tests/test_gpu_adjoint_ec.py)
 
