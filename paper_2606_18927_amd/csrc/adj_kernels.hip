@@ -765,11 +765,15 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_b(const double* __restrict__
   }
 }
 
+// y = a y + b x; with a = 0 the old y is not read (a cleared or never written
+// buffer may hold anything), with x null y = a y.
 __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b,
                         long long n) {
   for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
-       t += static_cast<long long>(gridDim.x) * blockDim.x)
-    y[t] = a * y[t] + b * x[t];
+       t += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const double ay = a == 0.0 ? 0.0 : a * y[t];
+    y[t] = x ? ay + b * x[t] : ay;
+  }
 }
 
 template <int N>

@@ -241,9 +241,9 @@ dg_status reverse_stages(dg_ctx* c, In stage_in, double dt, const double* lam_np
   if ((st = hip_check(c, hipMemcpyAsync(c->lamU, lam_np1, bytes, hipMemcpyDeviceToDevice, c->stream),
                       "lam copy")) != DG_OK)
     return st;
-  // cot_4 = B_4 lamU (A_5 = 0); each later cot_{s-1} = A_s cot_s + B_{s-1} lamU is
-  // formed by the VJP kernel of stage s right after it updates lamU
-  if ((st = hip_check(c, hipMemsetAsync(c->lamG, 0, bytes, c->stream), "clear lamG")) != DG_OK) return st;
+  // cot_4 = B_4 lamU (A_5 = 0; a = 0 does not read the old lamG); each later
+  // cot_{s-1} = A_s cot_s + B_{s-1} lamU is formed by the VJP kernel of stage s
+  // right after it updates lamU
   if ((st = hip_check(c, dg::launch_axpby(c->lamG, c->lamU, 0.0, kRkB[4], 5 * c->n_dof, c->stream),
                       "axpby kernel")) != DG_OK)
     return st;
@@ -465,7 +465,8 @@ dg_status dg_set_state(dg_ctx* c, const double* U) {
   if ((st = hip_check(c, hipMemcpyAsync(c->U[0], U, bytes, hipMemcpyDeviceToDevice, c->stream),
                       "set_state copy")) != DG_OK)
     return st;
-  return hip_check(c, hipMemsetAsync(c->G, 0, bytes, c->stream), "clear G");
+  // cleared by a kernel: a caller may capture this call into a graph
+  return hip_check(c, dg::launch_axpby(c->G, nullptr, 0.0, 0.0, 5 * c->n_dof, c->stream), "clear G");
 }
 
 dg_status dg_get_state(const dg_ctx* cc, double* U) {

@@ -73,7 +73,9 @@ hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBa
                           const double* U, const double* lam, double* gbar, double* ubar,
                           double* out, bool accumulate, double scale, hipStream_t s,
                           double* cot = nullptr, double cot_a = 0.0, double cot_b = 0.0);
-// y = a y + b x over n doubles.
+// y = a y + b x over n doubles; a = 0 does not read y and x = null drops the
+// b x term, so (y, null, 0, 0) clears y (a kernel, not a memset node, for
+// callers that capture the stream into a graph).
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
 // Curvilinear hexahedra (curv_kernels.hip, FP64): metric terms from the node

@@ -32,7 +32,9 @@
 // the differences taken in FP64), and the exactly known contributions of the
 // reference values are added back: sum_m D_im = 0 removes p_ref from the
 // momentum flux differences and leaves 2 e_ref sum_m D_im (rho u_d)# +
-// p_ref sum_m D_im u_d,m in the energy equation.
+// p_ref sum_m D_im u_d,m in the energy equation.  The entropy-conserving
+// pair does the same with its own reference quantities (beta - beta_ref and
+// rho (p - p_ref) / p per node, internal energy as e_ref).
 //
 // Workgroup ids are remapped so that each XCD (own L2) covers one contiguous
 // range of elements, keeping face neighbours in the same L2.

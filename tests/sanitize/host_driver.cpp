@@ -145,8 +145,12 @@ int main() {
     dg_physics q = gas();
     q.gamma = 1.0;
     EXPECT(dg_init_mesh(&ok.d, &q, nullptr, &c) == DG_EINVAL);
-    q = gas(DG_MIXED, DG_FLUX_EC_ROE);
+    q = gas(DG_MIXED_NOREF, DG_FLUX_EC_ROE);
     EXPECT(dg_init_mesh(&ok.d, &q, nullptr, &c) == DG_EUNSUPPORTED);
+    q = gas(DG_MIXED, DG_FLUX_EC_ROE);
+    c = nullptr;
+    EXPECT(dg_init_mesh(&ok.d, &q, nullptr, &c) == DG_OK);
+    if (c) dg_free(c);
     q = gas();
     q.viscosity = DG_VISC_SUTHERLAND;
     q.T_ref = 1.0;
