@@ -292,6 +292,49 @@ def run_precision(wl, U, dt, precision, steps, warmup):
     return res, Ud
 
 
+def run_small_graph(steps: int, warmup: int):
+    """The launch-bound small case (N = 3 Taylor-Green on 4^3 elements, 4,096
+    DOF, ten launches per RK step): steps pairs of RK steps launched with
+    dg_rk_step, then replayed from a HIP graph of two steps
+    (dg_rk_graph_build / dg_rk_graph_launch)."""
+    import torch
+
+    from paper_2606_18927_amd import dgsem, workloads
+
+    wl = workloads.WORKLOADS["tgv_n3_4x4x4"]
+    xi, _ = dgsem.lgl(wl.N)
+    U, dt = workloads.make_state(wl, xi)
+    Ud = torch.as_tensor(U.reshape(-1)).cuda()
+    S = dgsem.solver_for(wl)
+    S.set_state(Ud)
+
+    def timed(run):
+        run(warmup)
+        S.sync()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(S.stream)
+        run(steps)
+        b.record(S.stream)
+        S.sync()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    def eager(k):
+        for _ in range(k):
+            S.rk_step(dt, 2)
+
+    t_eager = timed(eager)
+    S.rk_graph_build(dt, 2)
+    t_graph = timed(lambda k: S.rk_graph_launch(k))
+    per = lambda ms: ms * 1e6 / (S.n_dof * 2 * steps * 5)  # noqa: E731
+    res = {"workload": wl.name, "dof": S.n_dof, "rk_steps": 2 * steps,
+           "eager_ns_per_dof_stage": per(t_eager), "graph_ns_per_dof_stage": per(t_graph),
+           "eager_us_per_step": t_eager * 1e3 / (2 * steps), "graph_us_per_step": t_graph * 1e3 / (2 * steps),
+           "speedup": t_eager / t_graph}
+    del S
+    return res
+
+
 def run_adjoint(steps: int, K: int):
     """Adjoint/forward time ratio on the N=5, 48x32x48 stretched channel:
     mixed-precision forward RK rollout, then the checkpointed FP64 adjoint of
@@ -444,6 +487,11 @@ def main():
                   flush=True)
         except dgsem.DgsemError as e:
             curved = {"error": str(e)}
+    small = None
+    if wl.name == "tgv_n7_32x32x32":
+        small = run_small_graph(100, 5)
+        print(f"[bench] {small['workload']}: {small['eager_us_per_step']:.1f} us/step launched, "
+              f"{small['graph_us_per_step']:.1f} us/step from a HIP graph", file=sys.stderr, flush=True)
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint(args.adjoint_steps, 25)
@@ -501,6 +549,7 @@ def main():
         "curved": curved,
         "wall_model": wall,
         "adjoint": adjoint,
+        "small_case_graph": small,
         "context_mi300a_pid_ns": {"range": [2.457, 4.260], "note": "paper Table 1, 32 APUs, N=7 free stream"},
     }
     print(json.dumps(out))

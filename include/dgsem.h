@@ -171,6 +171,20 @@ dg_status dg_eval_lift(dg_ctx* ctx, const double* U_dev, double* grad_dev);
  * U <- U + B_s G.  t is the time at the start.                               */
 dg_status dg_rk_step(dg_ctx* ctx, double t, double dt, int nsteps);
 
+/* dg_rk_step captured once into a HIP graph, for loops that launch-bound
+ * (small meshes: 10 kernel launches per step).  dg_rk_graph_build records
+ * nsteps (even, >= 2) steps of size dt on a private stream and instantiates
+ * them; nothing runs and the state is unchanged.  dg_rk_graph_launch enqueues
+ * the graph `repeats` times on the context's stream: each repeat advances the
+ * state by nsteps steps exactly as dg_rk_step would (same kernels, same
+ * order, bitwise the same result).  The graph holds the workspace pointers: a
+ * new dg_bind_workspace or dg_rk_graph_build drops it, dg_free releases it.
+ * Errors: DG_EINVAL (odd or < 2 nsteps, non-finite dt, repeats < 0),
+ * DG_ESTATE (no workspace; no graph; build while dg_timing is active),
+ * DG_EHIP (capture or instantiation refused by the runtime).              */
+dg_status dg_rk_graph_build(dg_ctx* ctx, double dt, int nsteps);
+dg_status dg_rk_graph_launch(dg_ctx* ctx, int repeats);
+
 /* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs.  Needs a
  * workspace bound with_adjoint.  FP64 arithmetic.  The VJP calls cover
  * axis-aligned elements with isothermal or periodic ends (either flux pair,

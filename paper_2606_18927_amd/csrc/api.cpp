@@ -151,6 +151,14 @@ void mark(dg_ctx* c, int cls) {
   if (hipEventRecord(c->events[k], c->stream) == hipSuccess) c->event_class.push_back(cls);
 }
 
+// Release the captured RK graph (its kernel arguments point into the bound
+// workspace, so a new binding drops it too).
+void drop_graph(dg_ctx* c) {
+  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  c->graph = nullptr;
+  c->graph_steps = 0;
+}
+
 dg_status need_bound(dg_ctx* c) {
   if (!c) return DG_EINVAL;
   if (!c->bound) return fail(c, DG_ESTATE, "no workspace bound (dg_bind_workspace)");
@@ -388,6 +396,7 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
   const Layout L = layout(c);
   const size_t need = with_adjoint ? L.adj_end : L.fwd_end;
   if (bytes < need) return fail(c, DG_EINVAL, "workspace too small");
+  drop_graph(c);
   char* ws = static_cast<char*>(dev_ptr);
   c->ws = ws;
   c->ws_bytes = bytes;
@@ -688,11 +697,72 @@ dg_status dg_sync(dg_ctx* c) {
 
 const char* dg_last_error(const dg_ctx* c) { return c ? c->err.c_str() : "null context"; }
 
+dg_status dg_rk_graph_build(dg_ctx* c, double dt, int nsteps) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (nsteps < 2 || nsteps % 2 != 0 || !std::isfinite(dt))
+    return fail(c, DG_EINVAL, "rk graph: nsteps must be even and >= 2, dt finite");
+  if (c->timing) return fail(c, DG_ESTATE, "rk graph: not while dg_timing is active");
+  drop_graph(c);
+  // The stages are captured on a private stream (the context's may be the
+  // null stream, which cannot be captured); launches later go to the
+  // context's stream.  5 nsteps stages, an even number, leave the state in
+  // the buffer the graph reads, so the graph can be replayed back to back.
+  hipStream_t cap = nullptr;
+  if ((st = hip_check(c, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "rk graph stream")) != DG_OK)
+    return st;
+  const hipStream_t saved = c->stream;
+  const int cur0 = c->cur;
+  hipGraph_t g = nullptr;
+  st = hip_check(c, hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "rk graph capture");
+  if (st == DG_OK) {
+    c->stream = cap;
+    const dg_status run = dg_rk_step(c, 0.0, dt, nsteps);
+    c->stream = saved;
+    const dg_status end = hip_check(c, hipStreamEndCapture(cap, &g), "rk graph capture end");
+    st = run != DG_OK ? run : end;
+  }
+  c->cur = cur0;
+  if (st == DG_OK)
+    st = hip_check(c, hipGraphInstantiate(&c->graph, g, nullptr, nullptr, 0), "rk graph instantiate");
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipStreamDestroy(cap);
+  if (st != DG_OK) {
+    c->graph = nullptr;
+    return st;
+  }
+  c->graph_steps = nsteps;
+  c->graph_cur = cur0;
+  return DG_OK;
+}
+
+dg_status dg_rk_graph_launch(dg_ctx* c, int repeats) {
+  dg_status st = need_bound(c);
+  if (st != DG_OK) return st;
+  if (!c->graph) return fail(c, DG_ESTATE, "no rk graph (dg_rk_graph_build)");
+  if (repeats < 0) return fail(c, DG_EINVAL, "repeats < 0");
+  if (repeats == 0) return DG_OK;
+  if (c->cur != c->graph_cur) {
+    // the state sits in the other buffer (dg_set_state, an odd dg_rk_step):
+    // move it to the one the graph reads
+    const size_t bytes = 5 * static_cast<size_t>(c->n_dof) * sizeof(double);
+    if ((st = hip_check(c, hipMemcpyAsync(c->U[c->graph_cur], c->U[c->cur], bytes, hipMemcpyDeviceToDevice,
+                                          c->stream),
+                        "rk graph state copy")) != DG_OK)
+      return st;
+    c->cur = c->graph_cur;
+  }
+  for (int r = 0; r < repeats; ++r)
+    if ((st = hip_check(c, hipGraphLaunch(c->graph, c->stream), "rk graph launch")) != DG_OK) return st;
+  return DG_OK;
+}
+
 dg_status dg_free(dg_ctx* c) {
   if (c) {
     for (hipEvent_t e : c->events)
       if (e) (void)hipEventDestroy(e);
     if (c->event_start) (void)hipEventDestroy(c->event_start);
+    drop_graph(c);
   }
   delete c;
   return DG_OK;

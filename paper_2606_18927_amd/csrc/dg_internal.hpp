@@ -160,5 +160,11 @@ struct dg_ctx {
   hipEvent_t event_start = nullptr;
   bool timing = false;
 
+  // RK steps captured into a HIP graph (dg_rk_graph_build): the instantiated
+  // graph, its step count and the state buffer it reads and leaves the result in
+  hipGraphExec_t graph = nullptr;
+  int graph_steps = 0;
+  int graph_cur = 0;
+
   std::string err;
 };

@@ -63,6 +63,8 @@ _SIGNATURES = {
     "dg_eval_rhs": (_I, [_P, _P, _P, _D]),
     "dg_eval_lift": (_I, [_P, _P, _P]),
     "dg_rk_step": (_I, [_P, _D, _D, _I]),
+    "dg_rk_graph_build": (_I, [_P, _D, _I]),
+    "dg_rk_graph_launch": (_I, [_P, _I]),
     "dg_eval_rhs_vjp": (_I, [_P, _P, _P, _P, _D]),
     "dg_rk_step_vjp": (_I, [_P, _P, _D, _D, _P, _P]),
     "dg_rk_record_stages": (_I, [_P, _P, _D, _D, _I, _P]),
@@ -234,6 +236,14 @@ class Solver:
 
     def rk_step(self, dt: float, nsteps: int = 1, t: float = 0.0):
         self._check(lib().dg_rk_step(self._ctx, t, dt, nsteps), "dg_rk_step")
+
+    def rk_graph_build(self, dt: float, nsteps: int = 2):
+        """Capture nsteps (even) RK steps into a HIP graph (nothing runs)."""
+        self._check(lib().dg_rk_graph_build(self._ctx, dt, nsteps), "dg_rk_graph_build")
+
+    def rk_graph_launch(self, repeats: int = 1):
+        """Advance the state by repeats x the captured steps (asynchronous)."""
+        self._check(lib().dg_rk_graph_launch(self._ctx, repeats), "dg_rk_graph_launch")
 
     def eval_rhs_vjp(self, U: torch.Tensor, lam: torch.Tensor, out: torch.Tensor | None = None,
                      t: float = 0.0) -> torch.Tensor:
