@@ -320,8 +320,12 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
 }
 
 // ------------------------------------------------------- right-hand side / RK
+// The Kennedy-Gruber instances fit 128 registers (four waves per SIMD); the
+// entropy-conserving ones are bounded for three: at 128 they spilled 46-58
+// values per lane, and at degree 7 one workgroup per CU without spills is 17 %
+// faster than two with them.
 template <int N, bool RK, bool VISC, bool EC>
-__global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs_curv(
+__global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(EC ? 3 : 4))) void k_rhs_curv(
     const double* __restrict__ U, const double* __restrict__ ffv, double* __restrict__ out,
     double* __restrict__ U_out, DevMesh mesh, DevPhys ph, DevBasis basis, Stage st,
     int* __restrict__ status) {
