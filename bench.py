@@ -182,6 +182,8 @@ def run_wall_model(steps, warmup):
     out = {}
     r, Ud = run_precision(wl, U, dt, "fp64", steps, warmup)
     out["wall_model"] = _leg(wl.name, r)
+    r, _ = run_precision(wl, U, dt, "mixed", steps, warmup)
+    out["wall_model_mixed"] = _leg(wl.name + " (mixed)", r)
     r, _ = run_precision(wl_iso, U, dt, "fp64", steps, warmup)
     out["isothermal_constant_mu"] = _leg(wl_iso.name + " (fp64)", r)
     S = dgsem.solver_for(wl, precision="fp64")
@@ -468,7 +470,8 @@ def main():
         try:
             wall = run_wall_model(args.steps, args.warmup)
             print(f"[bench] wall model channel {wall['wall_model']['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage "
-                  f"(isothermal {wall['isothermal_constant_mu']['ns_per_dof_stage']*1e3:.1f}); "
+                  f"(mixed {wall['wall_model_mixed']['ns_per_dof_stage']*1e3:.1f}; "
+                  f"isothermal {wall['isothermal_constant_mu']['ns_per_dof_stage']*1e3:.1f}); "
                   f"k_wall_stress {wall['k_wall_stress']['ms_per_launch']*1e3:.1f} us", file=sys.stderr,
                   flush=True)
         except dgsem.DgsemError as e:

@@ -51,7 +51,7 @@ typedef enum {
 #define DG_BC_ISOTHERMAL_WALL 1
 #define DG_BC_WALL_MODEL 2   /* slip, adiabatic wall whose shear stress comes from the
                                 algebraic wall model (dg_wall_stress) evaluated on the
-                                state of every stage; FP64 only; no adjoint           */
+                                state of every stage; FP64 or mixed; no adjoint       */
 
 #define DG_FP64 0
 #define DG_MIXED 1
@@ -75,7 +75,7 @@ typedef enum {
                                  mu being the viscosity at T_ref; T_ref and S in the units
                                  of T; taken at each node's temperature (at a wall: the
                                  interior face node's; in the wall model: the wall
-                                 temperature's).  DG_FP64 only; the adjoint covers it      */
+                                 temperature's).  FP64 or mixed; the adjoint covers it    */
 
 typedef struct dg_ctx dg_ctx;
 

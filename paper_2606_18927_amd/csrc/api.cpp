@@ -324,12 +324,10 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   if (phys->viscosity == DG_VISC_SUTHERLAND) {
     if (!(phys->T_ref > 0.0) || !(phys->S >= 0.0) || !std::isfinite(phys->T_ref) || !std::isfinite(phys->S))
       return DG_EINVAL;
-    if (phys->precision != DG_FP64) return DG_EUNSUPPORTED;
   }
   const bool wall_model = mesh->bc[0] == DG_BC_WALL_MODEL || mesh->bc[1] == DG_BC_WALL_MODEL ||
                           mesh->bc[2] == DG_BC_WALL_MODEL;
   if (wall_model && (mesh->wm_node < 1 || mesh->wm_node > mesh->N)) return DG_EINVAL;
-  if (wall_model && phys->precision != DG_FP64) return DG_EUNSUPPORTED;
   if (mesh->bc[0] == DG_BC_ISOTHERMAL_WALL || mesh->bc[1] == DG_BC_ISOTHERMAL_WALL ||
       mesh->bc[2] == DG_BC_ISOTHERMAL_WALL) {
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;

@@ -133,10 +133,11 @@ __device__ inline void viscous_flux_tau(R u, R v, R w, const R tau[6], const R q
 }
 
 // Lifting corrections of one face task: (q* - q_own) (+-1/w_end), FP64.
-__device__ inline void lifting_correction(const Prim& Po, const Prim& Pn, bool wall, double T_wall,
-                                          bool up, double inv_w, double out[4]) {
+__device__ inline void lifting_correction(const Prim& Po, const Prim& Pn, bool wall, const DevMesh& m,
+                                          int d, bool up, double inv_w, double out[4]) {
   const double qo[4] = {Po.u, Po.v, Po.w, Po.T};
-  double qs[4] = {0.0, 0.0, 0.0, T_wall};
+  double qs[4];
+  wall_lifting_value(m, d, qo, qs);  // the wall's value (isothermal or wall-model wall)
   if (!wall) {
     const double qn[4] = {Pn.u, Pn.v, Pn.w, Pn.T};
 #pragma unroll
@@ -322,8 +323,11 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
     const V2 uv = sq[le][0][l], wT = sq[le][1][l];
     const R u = uv.x, v = uv.y, w = wT.x;
     R mu = static_cast<R>(ph.mu), kappa = static_cast<R>(ph.kappa);
-    if (ph.suth) {  // FP64 contexts only: LDS holds T itself (no reference value)
-      const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(wT.y)));
+    if (ph.suth) {
+      // mu(T) at the node's temperature: in FP64 the LDS holds T itself, in
+      // mixed precision the FP64 copy holds it
+      const double T = MIXED ? sqd[le][3][i + NP * (j + NP * k)] : static_cast<double>(wT.y);
+      const R r = static_cast<R>(viscosity_ratio(ph, T));
       mu *= r;
       kappa *= r;
     }
@@ -836,7 +840,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       for (int v = 0; v < 5; ++v) sO[ft.le][ft.f][v][ft.ab] = so[v];
       if (VISC) {
         double corr[4];
-        lifting_correction(primitives(so, ph), primitives(sn, ph), fwall, mesh.T_wall, ft.up,
+        lifting_correction(primitives(so, ph), primitives(sn, ph), fwall, mesh, ft.d, ft.up,
                            basis.inv_w_end, corr);
 #pragma unroll
         for (int c = 0; c < 4; ++c) ssq[ft.le][ft.f][c][ft.ab] = static_cast<R>(corr[c]);
@@ -851,14 +855,13 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
   for (int q = 0; q < NSP; ++q) own[q].x = own[q].y = R(0);
   R uo = R(0), vo = R(0), wo = R(0);  // own velocity (full values)
-  double p_ref = 0.0, e_ref = 0.0, beta_ref = 0.0;
+  double p_ref = 0.0, e_ref = 0.0, beta_ref = 0.0, T_ref = 0.0;
   int ex = ex0, ey = ey0, ez = ez0;
   R* sT = reinterpret_cast<R*>(&sfv[le][0][0]);
   if (active) {
     if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
     const Prim P = primitives(u0, ph);
     if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
-    double T_ref;
     element_ref<R>(s0, ph, p_ref, e_ref, T_ref);
     uo = static_cast<R>(P.u);
     vo = static_cast<R>(P.v);
@@ -932,8 +935,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       lifted_gradients_half<N, R, V2, !EC>(sD, sp[le], sT, ssq[le], i, j, k,
                                       static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
                                       static_cast<R>(mesh.s[2][ez]), g);
-      if (ph.suth) {  // FP64 contexts only: sT holds T itself (no reference value)
-        const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(sT[l])));
+      if (ph.suth) {  // sT holds T - T_ref (T_ref = 0 in FP64)
+        const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(sT[l]) + T_ref));
         stress<R>(g, mu * r, kappa * r, tau, qT);
       } else {
         stress<R>(g, mu, kappa, tau, qT);

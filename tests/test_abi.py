@@ -94,11 +94,13 @@ def test_init_mesh_validation_errors(L):
         L.dg_free(ctx)
     assert _init(L, d, _phys(flux=1, precision=2))[0] == dgsem.DG_EUNSUPPORTED
     assert _init(L, d, _phys(flux=2))[0] == dgsem.DG_EINVAL
-    # viscosity law: Sutherland's needs T_ref > 0 and S >= 0, and is FP64 only
+    # viscosity law: Sutherland's needs T_ref > 0 and S >= 0
     st, ctx = _init(L, d, _phys(viscosity=1, T_ref=1.0, S=0.38))
     assert st == dgsem.DG_OK
     L.dg_free(ctx)
-    assert _init(L, d, _phys(viscosity=1, T_ref=1.0, S=0.38, precision=1))[0] == dgsem.DG_EUNSUPPORTED
+    st, ctx = _init(L, d, _phys(viscosity=1, T_ref=1.0, S=0.38, precision=1))  # mixed precision too
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
     for bad in (dict(viscosity=2), dict(viscosity=1, T_ref=0.0, S=0.38), dict(viscosity=1, T_ref=1.0, S=-1.0),
                 dict(viscosity=1, T_ref=float("inf"), S=0.38)):
         assert _init(L, d, _phys(**bad))[0] == dgsem.DG_EINVAL, bad

@@ -6,7 +6,7 @@ Right-hand side: relative L2 <= 1e-12 per variable on random states (T varies
 by about 40 % across nodes) at N = 3, 5, 7, periodic and between isothermal
 walls, with both flux pairs; five RK steps; the wall-model stress and the
 operator with wall-model ends (mu at the wall temperature); the rejected
-combinations (mixed precision, bad constants).
+constants.
 """
 
 import numpy as np
@@ -118,10 +118,8 @@ def test_sutherland_rejected_combinations():
     need_gpu()
     mesh = Mesh(3, (uniform_faces(2, 0, 1),) * 3)
     g = _gas()
-    with pytest.raises(dgsem.DgsemError) as ei:
-        _solver(mesh, g, precision="mixed")
-    assert ei.value.status == dgsem.DG_EUNSUPPORTED
-    # (the adjoint covers Sutherland's law: tests/test_gpu_adjoint.py)
+    # (mixed precision covers Sutherland's law: tests/test_gpu_mixed_physics.py;
+    # the adjoint: tests/test_gpu_adjoint.py)
     for T_ref, Sg in ((0.0, 0.3), (1.0, -0.1), (float("nan"), 0.3)):
         spec = dgsem.MeshSpec(mesh.N, mesh.faces, mesh.bc, mesh.T_wall, mesh.wm_node)
         with pytest.raises(dgsem.DgsemError) as ei:

@@ -183,9 +183,7 @@ def test_wall_model_unsupported_combinations():
     mesh = Mesh(3, (uniform_faces(2, 0, 1), uniform_faces(2, -1, 1), uniform_faces(2, 0, 1)),
                 bc=("periodic", "wallmodel", "periodic"), wm_node=1)
     g = Gas(gamma=1.4, R=1.0, mu=1e-3, Pr=0.72)
-    with pytest.raises(dgsem.DgsemError) as ei:
-        _wm_solver(mesh, g, precision="mixed")
-    assert ei.value.status == dgsem.DG_EUNSUPPORTED
+    # (mixed precision covers the wall model: tests/test_gpu_mixed_physics.py)
     S = _wm_solver(mesh, g, with_adjoint=True)
     U = to_dev(np.ones((5,) + mesh.shape) * np.array([1, 0.1, 0, 0, 3.0])[:, None, None, None, None, None, None])
     with pytest.raises(dgsem.DgsemError) as ei:
