@@ -114,6 +114,22 @@ def time_steps(S, dt, steps, warmup):
     return ms, lift_ms, rk_ms, n_lift, n_rk
 
 
+def repeat_steps(S, dt, steps, reps=5):
+    """The same `steps` RK steps timed `reps` more times back to back (HIP
+    events on the context's stream): ms per run, for min / median."""
+    import torch
+    out = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(S.stream)
+        S.rk_step(dt, steps)
+        b.record(S.stream)
+        torch.cuda.synchronize()
+        out.append(a.elapsed_time(b))
+    S.sync()
+    return out
+
+
 def _leg(wl_name, r):
     return {"workload": wl_name, "ns_per_dof_stage": r["ns_per_dof_stage"], "ms_per_step": r["ms_per_step"],
             "rk_kernel_ms": r["rk_kernel_ms"], "face_kernel_ms": r["face_kernel_ms"],
@@ -264,7 +280,7 @@ def triad_gbs():
     return 24.0 * n / sec / 1e9
 
 
-def run_precision(wl, U, dt, precision, steps, warmup):
+def run_precision(wl, U, dt, precision, steps, warmup, repeats=False):
     import torch
 
     from paper_2606_18927_amd import dgsem
@@ -275,6 +291,7 @@ def run_precision(wl, U, dt, precision, steps, warmup):
     dof = S.n_dof
     stages = steps * 5
     ns = ms * 1e6 / (dof * stages)
+    reps = sorted(x * 1e6 / (dof * stages) for x in repeat_steps(S, dt, steps)) if repeats else None
     b = alg_bytes(precision, wl.N)
     rk_bytes = dof * (b["rk"] * (stages - steps) + b["rk_first"] * steps) / stages
     rk_avg_s = rk_ms / 1e3 / n_rk
@@ -289,6 +306,9 @@ def run_precision(wl, U, dt, precision, steps, warmup):
         / (ms / 1e3) / 1e9,
         "rk_bytes_per_launch": rk_bytes,
     }
+    if reps:
+        res["repeats_ns_per_dof_stage"] = {"n": len(reps), "min": reps[0], "median": reps[len(reps) // 2],
+                                           "max": reps[-1]}
     del S
     torch.cuda.empty_cache()
     return res, Ud
@@ -432,12 +452,14 @@ def main():
     print(f"[bench] {wl.name}: {wl.n_dof} DOF, dt={dt:.4e}, steps={args.steps}, warmup={args.warmup}",
           file=sys.stderr, flush=True)
 
-    fp64, Ud = run_precision(wl, U, dt, "fp64", args.steps, args.warmup)
-    print(f"[bench] fp64 {fp64['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
+    fp64, Ud = run_precision(wl, U, dt, "fp64", args.steps, args.warmup, repeats=True)
+    rp = fp64["repeats_ns_per_dof_stage"]
+    print(f"[bench] fp64 {fp64['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage (5 more runs: min {rp['min']*1e3:.1f}, "
+          f"median {rp['median']*1e3:.1f})", file=sys.stderr, flush=True)
     mixed = None
     if not args.no_mixed:
         try:
-            mixed, _ = run_precision(wl, U, dt, "mixed", args.steps, args.warmup)
+            mixed, _ = run_precision(wl, U, dt, "mixed", args.steps, args.warmup, repeats=True)
             print(f"[bench] mixed {mixed['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr, flush=True)
         except dgsem.DgsemError as e:
             mixed = {"error": str(e)}
@@ -523,6 +545,7 @@ def main():
         "config": {"workload": wl.name, "N": wl.N, "elements": list(wl.nelem), "dof": wl.n_dof,
                    "rk_stages_per_step": 5, "precision": "fp64"},
         "dof_stage_per_s": 1e9 / value,
+        "repeats_ns_per_dof_stage": fp64["repeats_ns_per_dof_stage"],
         "roofline": {
             "bound": "hbm",
             "kernel": "k_rhs (fused RHS + RK stage)",
