@@ -170,13 +170,27 @@ def test_free_stream_and_determinism():
     assert a.abs().max().item() < 1e-13 * scale
 
 
-def test_nonphysical_state_is_reported():
+@pytest.mark.parametrize("kind", ["fp64", "mixed", "ec_roe", "ec_roe_mixed", "curved", "rk_step"])
+def test_nonphysical_state_is_reported(kind):
+    """A negative density at one node is latched by the right-hand-side kernel
+    of every instance and reported by dg_sync, which then clears it."""
     need_gpu()
     mesh, g, U = _case_random(3, (2, 2, 2), seed=3)
     U = U.copy()
     U[0, 0, 0, 0, 1, 1, 1] = -1.0
-    S = _solver(mesh, g)
-    S.eval_rhs(to_dev(U))
+    kw = {"mixed": dict(precision="mixed"), "ec_roe": dict(flux="ec_roe"),
+          "ec_roe_mixed": dict(flux="ec_roe", precision="mixed")}.get(kind, {})
+    if kind == "curved":
+        X = np.stack([c.numpy() for c in mesh.coords()])
+        spec = dgsem.MeshSpec(mesh.N, None, mesh.bc, mesh.T_wall, 1, X)
+        S = dgsem.Solver(spec, g.gamma, g.R, g.mu, g.Pr)
+    else:
+        S = _solver(mesh, g, **kw)
+    if kind == "rk_step":
+        S.set_state(to_dev(U))
+        S.rk_step(1e-6, 1)
+    else:
+        S.eval_rhs(to_dev(U))
     with pytest.raises(dgsem.DgsemError) as ei:
         S.sync()
     assert ei.value.status == dgsem.DG_ENONPHYS
