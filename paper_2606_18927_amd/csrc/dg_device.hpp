@@ -200,11 +200,13 @@ __device__ inline double rcp_nr(double x) {
 // f = (a - b) / (a + b) (ln(a / b) = 2 atanh f).  For f^2 < 1e-4 F is its
 // series 1 + f^2/3 + f^4/5 + f^6/7 and 1 / F the series
 // 1 - f^2/3 - 4 f^4/45 - 44 f^6/945 (first dropped terms below 1.2e-17 and
-// 3.1e-18), so the common case costs two reciprocals and no logarithm.
+// 3.1e-18), so the common case costs one reciprocal and no logarithm.
 __device__ inline void ec_means(double ra, double rb, double ba, double bb, double& rho_ln,
                                 double& inv_beta_ln, double& p_hat) {
   const double sr = ra + rb, sb = ba + bb;
-  const double ir = rcp_nr(sr), ib = rcp_nr(sb);
+  // both reciprocals from one: 1 / (sr sb) times the other sum
+  const double x = rcp_nr(sr * sb);
+  const double ir = sb * x, ib = sr * x;
   const double fr = (ra - rb) * ir, fb = (ba - bb) * ib;
   const double ur = fr * fr, ub = fb * fb;
   rho_ln = 0.5 * sr * (1.0 - ur * (1.0 / 3.0 + ur * (4.0 / 45.0 + ur * (44.0 / 945.0))));

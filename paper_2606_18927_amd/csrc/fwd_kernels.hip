@@ -622,7 +622,8 @@ __device__ inline void volume_sweep_ec_mixed(const float2 (&own)[4], int i, int 
     const float2 b0 = sp[0][lm], b1 = sp[1][lm], b2 = sp[2][lm], b3 = sp[3][lm];
     const float sr = own[0].x + b0.x, sdb = own[2].x + b2.x;
     const float sb = 2.0f * beta_ref + sdb;
-    const float ir = __builtin_amdgcn_rcpf(sr), ib = __builtin_amdgcn_rcpf(sb);
+    const float x = __builtin_amdgcn_rcpf(sr * sb);
+    const float ir = sb * x, ib = sr * x;
     const float fr = (own[0].x - b0.x) * ir, fb = (own[2].x - b2.x) * ib;
     const float ur = fr * fr, ub = fb * fb;
     float G = 1.0f - ur * (1.0f / 3.0f + ur * (4.0f / 45.0f + ur * (44.0f / 945.0f)));
