@@ -29,21 +29,34 @@ from .dgsem import Solver
 __all__ = ["RKRollout", "rollout", "kinetic_energy_gradient"]
 
 
+def _segments_to_record(solver: Solver, nsteps: int, K: int, stage_memory_bytes) -> int:
+    """How many trailing segments record their stages in the forward pass:
+    those whose (K, 5, 5 n_dof) buffers fit in stage_memory_bytes (None: one,
+    the buffer the backward pass needs anyway)."""
+    nseg = -(-nsteps // K)
+    if stage_memory_bytes is None:
+        return 1
+    per = K * 25 * solver.n_dof * 8
+    return max(1, min(nseg, int(stage_memory_bytes // per)))
+
+
 def _forward_states(solver: Solver, U0: torch.Tensor, dt: float, nsteps: int, K: int,
-                    record_stages: bool = True):
+                    record_stages: bool = True, stage_memory_bytes=None):
     """Run the rollout; return U_T, the checkpoints {step: state} and, with
-    record_stages, the stage-state buffer (K, 5, 5 n_dof) holding the last
-    segment's stages: that segment is recorded during the forward pass, so
-    the backward pass does not recompute it (same kernels, same states)."""
+    record_stages, {segment start: stage-state buffer (K, 5, 5 n_dof)} of the
+    trailing segments recorded during the forward pass, which the backward
+    pass then does not recompute (same kernels, same states)."""
     ckpts = {0: U0.detach().clone()}
     solver.set_state(U0)
-    buf = None
+    nrec = _segments_to_record(solver, nsteps, K, stage_memory_bytes) if record_stages else 0
+    first_rec = (-(-nsteps // K) - nrec) * K  # start of the first recorded segment
+    bufs = {}
     done = 0
     while done < nsteps:
         n = min(K, nsteps - done)
-        if record_stages and done + n == nsteps:
-            buf = torch.empty((K, 5, 5 * solver.n_dof), dtype=torch.float64, device=U0.device)
-            solver.rk_record_stages(ckpts[done], dt, n, out=buf)
+        if record_stages and done >= first_rec:
+            bufs[done] = torch.empty((K, 5, 5 * solver.n_dof), dtype=torch.float64, device=U0.device)
+            solver.rk_record_stages(ckpts[done], dt, n, out=bufs[done])
         else:
             solver.rk_step(dt, n)
         done += n
@@ -51,21 +64,24 @@ def _forward_states(solver: Solver, U0: torch.Tensor, dt: float, nsteps: int, K:
             ckpts[done] = solver.get_state()
     UT = solver.get_state()
     solver.sync()
-    return UT, ckpts, buf
+    return UT, ckpts, bufs
 
 
 def _backward_states(solver: Solver, ckpts: dict, dt: float, nsteps: int, K: int,
-                     lam_T: torch.Tensor, record_stages: bool = True, buf=None) -> torch.Tensor:
-    """lam_0 from lam_T; `buf`, if given, holds the last segment's recorded
-    stage states (from the forward pass)."""
+                     lam_T: torch.Tensor, record_stages: bool = True, bufs=None) -> torch.Tensor:
+    """lam_0 from lam_T; `bufs` holds the stage states recorded in the forward
+    pass ({segment start: buffer}); other segments are recomputed into one of
+    those buffers once it has been consumed."""
     lam = lam_T.detach().clone().contiguous()
     spare = torch.empty_like(lam)
     starts = sorted(ckpts)
-    last = starts[-1]
+    bufs = dict(bufs or {})
+    buf = None
     for s0 in reversed(starts):
         s1 = min(s0 + K, nsteps)
         if record_stages:
-            if s0 == last and buf is not None:
+            if s0 in bufs:
+                buf = bufs.pop(s0)
                 stages = buf[: s1 - s0]
             else:
                 if buf is None:
@@ -91,32 +107,38 @@ def _backward_states(solver: Solver, ckpts: dict, dt: float, nsteps: int, K: int
 
 class RKRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, solver, dt, nsteps, checkpoint_every, record_stages=True):
+    def forward(ctx, U0, solver, dt, nsteps, checkpoint_every, record_stages=True, stage_memory_bytes=None):
         K = max(1, int(checkpoint_every) if checkpoint_every else nsteps)
-        UT, ckpts, buf = _forward_states(solver, U0.contiguous(), dt, nsteps, K, bool(record_stages))
-        ctx.solver, ctx.dt, ctx.nsteps, ctx.K, ctx.ckpts, ctx.buf = solver, dt, nsteps, K, ckpts, buf
+        UT, ckpts, bufs = _forward_states(solver, U0.contiguous(), dt, nsteps, K, bool(record_stages),
+                                          stage_memory_bytes)
+        ctx.solver, ctx.dt, ctx.nsteps, ctx.K, ctx.ckpts, ctx.bufs = solver, dt, nsteps, K, ckpts, bufs
         ctx.record_stages = bool(record_stages)
         return UT
 
     @staticmethod
     def backward(ctx, gUT):
         lam0 = _backward_states(ctx.solver, ctx.ckpts, ctx.dt, ctx.nsteps, ctx.K, gUT,
-                                ctx.record_stages, ctx.buf)
-        ctx.ckpts = ctx.buf = None
-        return lam0, None, None, None, None, None
+                                ctx.record_stages, ctx.bufs)
+        ctx.ckpts = ctx.bufs = None
+        return lam0, None, None, None, None, None, None
 
 
 def rollout(U0: torch.Tensor, solver: Solver, dt: float, nsteps: int, checkpoint_every: int = 0,
-            record_stages: bool = True):
-    return RKRollout.apply(U0, solver, dt, nsteps, checkpoint_every, record_stages)
+            record_stages: bool = True, stage_memory_bytes=None):
+    """U_T of the rollout with the checkpointed backward pass.  stage_memory_bytes
+    lets the forward pass record the stages of as many trailing segments as fit
+    (K 25 n_dof doubles each; default: one), which are then not recomputed."""
+    return RKRollout.apply(U0, solver, dt, nsteps, checkpoint_every, record_stages, stage_memory_bytes)
 
 
 def kinetic_energy_gradient(solver: Solver, U0: torch.Tensor, dt: float, nsteps: int,
-                            checkpoint_every: int = 0, record_stages: bool = True):
-    """(J(U_T), dJ/dU0) for the volume-averaged kinetic energy J after nsteps."""
+                            checkpoint_every: int = 0, record_stages: bool = True, stage_memory_bytes=None):
+    """(J(U_T), dJ/dU0) for the volume-averaged kinetic energy J after nsteps
+    (stage_memory_bytes as in ``rollout``)."""
     K = max(1, checkpoint_every or nsteps)
-    UT, ckpts, buf = _forward_states(solver, U0.contiguous(), dt, nsteps, K, record_stages)
+    UT, ckpts, bufs = _forward_states(solver, U0.contiguous(), dt, nsteps, K, record_stages,
+                                      stage_memory_bytes)
     J = solver.kinetic_energy(UT)
     lam_T = solver.kinetic_energy_grad(UT)
-    lam0 = _backward_states(solver, ckpts, dt, nsteps, K, lam_T, record_stages, buf)
+    lam0 = _backward_states(solver, ckpts, dt, nsteps, K, lam_T, record_stages, bufs)
     return J, lam0

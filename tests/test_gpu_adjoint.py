@@ -273,3 +273,21 @@ def test_channel_48x32x48_mixed_forward_adjoint_against_fp64():
     with open(os.path.join("gpurun_out", "channel_48_adjoint.json"), "w") as f:
         json.dump(res, f, indent=1)
     assert np.all(e < 1e-3)
+
+
+def test_segments_recorded_in_the_forward_pass_give_the_same_gradient():
+    """Recording one, two or all segments' stages during the forward pass
+    (instead of recomputing them in the backward pass) runs the same kernels on
+    the same states: the gradients are bitwise equal."""
+    need_gpu()
+    wl = custom("channel", 3, (2, 3, 2), seed=workloads.CHANNEL_SEED)
+    U, dt = state(wl)
+    S = dgsem.solver_for(wl, with_adjoint=True)
+    Ud = to_dev(U)
+    per = 2 * 25 * S.n_dof * 8  # K = 2
+    grads = []
+    for budget in (None, 2 * per, 3 * per):
+        J, g = kinetic_energy_gradient(S, Ud, dt, 6, checkpoint_every=2, stage_memory_bytes=budget)
+        grads.append(g)
+    S.sync()
+    assert all(torch.equal(grads[0], x) for x in grads[1:])

@@ -88,3 +88,19 @@ def test_missing_library_fails_loudly(monkeypatch):
     with pytest.raises(dgsem.DgsemError) as ei:
         dgsem.lib()
     assert ei.value.status == dgsem.DG_ESTATE
+
+
+def test_segments_recorded_in_the_forward_pass():
+    """The checkpointed adjoint records the trailing segments that fit the
+    stage-memory budget (K 25 n_dof doubles each), at least one, at most all."""
+    from types import SimpleNamespace
+
+    from paper_2606_18927_amd.autograd import _segments_to_record
+    S = SimpleNamespace(n_dof=1000)
+    per = 25 * 25 * 1000 * 8  # K = 25
+    assert _segments_to_record(S, 50, 25, None) == 1
+    assert _segments_to_record(S, 50, 25, 0) == 1
+    assert _segments_to_record(S, 50, 25, 2 * per) == 2
+    assert _segments_to_record(S, 50, 25, 10 * per) == 2
+    assert _segments_to_record(S, 51, 25, 10 * per) == 3
+    assert _segments_to_record(S, 60, 25, 2 * per + per // 2) == 2
