@@ -57,15 +57,15 @@ STORED_GRADIENT_BYTES_PER_DOF = 392.0
 
 # HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
 # counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
-# 128 x 14,193,237.8 TCC_EA0_RDREQ_128B + 64 x 2,526.7 RDREQ_64B, writes
+# 128 x 14,216,440.4 TCC_EA0_RDREQ_128B + 64 x 2,529.1 RDREQ_64B, writes
 # WRITE_SIZE 1,310,720 KiB.  Valid only for the kernel sources it was counted
 # on; reported as null once they change.
-COUNTED_TRAFFIC = {"sources_sha256_prefix": "ffa2525673c30f0a", "bytes_per_launch": 3159073430.0}
+COUNTED_TRAFFIC = {"sources_sha256_prefix": "8f9bdc31aa34ecaa", "bytes_per_launch": 3162043515.0}
 TRAFFIC_SOURCES = ("fwd_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 # The same for k_rhs_curv<7,true,true,false> on the curved workload
 # (profiles/k_rhs_curv_k_face_flux_curv_tgv_n7_32x32x32_curved.md): reads
-# 128 x 46,528,941.5 RDREQ_128B + 64 x 1,934.5 RDREQ_64B, writes 1,310,720 KiB.
-COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "3e73389d7f958c8b", "bytes_per_launch": 7298005602.0}
+# 128 x 46,930,789.5 RDREQ_128B + 64 x 1,966.6 RDREQ_64B, writes 1,310,720 KiB.
+COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "fbf41dc1c665f986", "bytes_per_launch": 7349444203.0}
 TRAFFIC_SOURCES_CURVED = ("curv_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 
 
