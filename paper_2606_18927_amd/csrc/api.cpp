@@ -152,9 +152,13 @@ void mark(dg_ctx* c, int cls) {
 }
 
 // Release the captured RK graph (its kernel arguments point into the bound
-// workspace, so a new binding drops it too).
+// workspace, so a new binding drops it too), after its launches on the
+// context's stream have finished.
 void drop_graph(dg_ctx* c) {
-  if (c->graph) (void)hipGraphExecDestroy(c->graph);
+  if (c->graph) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipGraphExecDestroy(c->graph);
+  }
   c->graph = nullptr;
   c->graph_steps = 0;
 }

@@ -100,3 +100,17 @@ def test_graph_argument_errors():
     assert ei.value.status == dgsem.DG_EINVAL
     S.rk_graph_launch(0)
     S.sync()
+
+
+def test_graph_released_with_launches_in_flight():
+    """Freeing the context (or binding a new workspace) right after launches
+    waits for them before the graph is destroyed."""
+    need_gpu()
+    wl = workloads.WORKLOADS["tgv_n3_4x4x4"]
+    U, dt = state(wl)
+    S = dgsem.solver_for(wl)
+    S.set_state(to_dev(U))
+    S.rk_graph_build(dt, 2)
+    S.rk_graph_launch(5)
+    S.close()
+    torch.cuda.synchronize()
