@@ -1,7 +1,7 @@
 // Host paths of the C ABI under AddressSanitizer and UBSan (CPU only): the
 // LGL tables, mesh and physics validation (including the host copies of the
 // face and node arrays), workspace sizing, wall-face counts and the
-// state errors of calls made before a workspace is bound.  Exit status 0
+// state errors of every call made before a workspace is bound.  Exit status 0
 // when every expectation holds.
 #include <cmath>
 #include <cstdio>
@@ -91,6 +91,18 @@ int main() {
       EXPECT(dg_set_state(c, dummy) == DG_ESTATE);
       EXPECT(dg_eval_rhs_vjp(c, dummy, dummy, dummy + 1, 0.0) == DG_ESTATE);
       EXPECT(dg_wall_stress(c, dummy, 1, dummy) == DG_ESTATE);
+      EXPECT(dg_get_state(c, dummy) == DG_ESTATE);
+      EXPECT(dg_eval_lift(c, dummy, dummy + 1) == DG_ESTATE);
+      EXPECT(dg_rk_step_vjp(c, dummy, 0.0, 1e-3, dummy, dummy + 1) == DG_ESTATE);
+      EXPECT(dg_rk_record_stages(c, dummy, 0.0, 1e-3, 1, dummy + 1) == DG_ESTATE);
+      EXPECT(dg_rk_step_vjp_stages(c, dummy, 0.0, 1e-3, dummy, dummy + 1) == DG_ESTATE);
+      EXPECT(dg_kinetic_energy(c, dummy, dummy + 1) == DG_ESTATE);
+      EXPECT(dg_kinetic_energy_grad(c, dummy, dummy + 1) == DG_ESTATE);
+      EXPECT(dg_rk_graph_build(c, 1e-3, 2) == DG_ESTATE);
+      EXPECT(dg_rk_graph_launch(c, 1) == DG_ESTATE);
+      double ms[2];
+      int cnt[2];
+      EXPECT(dg_timing_end(c, ms, cnt) == DG_ESTATE);  // no dg_timing_begin
       EXPECT(dg_last_error(c) != nullptr);
       EXPECT(dg_free(c) == DG_OK);
     }
