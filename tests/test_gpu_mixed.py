@@ -1,15 +1,16 @@
 """Mixed-precision forward (GPU): per-variable errors against FP64.
 
-Stated bound (derived in the design doc from FP32 rounding and the conditioning of
-the low-Mach operator): relative L2 error per conserved variable <= 1e-4 for
+Stated bound (FP32 rounding, 6e-8, times the conditioning of the low-Mach
+operator, about 1e3 once the reference subtraction has removed p ~ 71 and
+e ~ 179 from the FP32 sums): relative L2 error per conserved variable <= 1e-4 for
 Ut against the FP64 oracle, and <= 1e-4 for the change of the state over an RK
 run against the FP64 reference, with the reference-state subtraction on.
 Without the subtraction the errors must be larger (the subtraction is what
 keeps p ~ 1/(gamma Ma^2) from swamping FP32).
 
 The errors measured here are printed per variable (max abs and rel L2) and,
-for the full N = 7, 32^3 Taylor-Green run of 100 steps, written to
-gpurun_out/mixed_errors.json.
+for the full N = 7, 32^3 Taylor-Green run of 100 steps, written as
+mixed_errors.json to the folder named by DGSEM_RESULTS_DIR when that is set.
 """
 
 import json
@@ -94,11 +95,13 @@ def test_mixed_full_size_run_against_fp64():
     U0 = U.reshape(5, -1)
     rel_inc, mx = _table("tgv_n7_32^3 mixed vs fp64, 100 steps, increment", out["mixed"] - U0, out["fp64"] - U0)
     rel_state, _ = _table("tgv_n7_32^3 mixed vs fp64, 100 steps, state", out["mixed"], out["fp64"])
-    os.makedirs("gpurun_out", exist_ok=True)
     names = ["rho", "rho_u", "rho_v", "rho_w", "E"]
-    with open(os.path.join("gpurun_out", "mixed_errors.json"), "w") as f:
-        json.dump({"workload": wl.name, "steps": wl.nsteps,
-                   "increment_rel_l2": dict(zip(names, rel_inc.tolist())),
-                   "max_abs": dict(zip(names, mx.tolist())),
-                   "state_rel_l2": dict(zip(names, rel_state.tolist()))}, f, indent=1)
+    out_dir = os.environ.get("DGSEM_RESULTS_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "mixed_errors.json"), "w") as f:
+            json.dump({"workload": wl.name, "steps": wl.nsteps,
+                       "increment_rel_l2": dict(zip(names, rel_inc.tolist())),
+                       "max_abs": dict(zip(names, mx.tolist())),
+                       "state_rel_l2": dict(zip(names, rel_state.tolist()))}, f, indent=1)
     assert np.all(rel_inc < BOUND)
