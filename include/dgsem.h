@@ -44,7 +44,7 @@ typedef enum {
   DG_ESTATE = 2,        /* call order violated (e.g. no workspace bound yet)     */
   DG_EHIP = 3,          /* a HIP runtime call failed (dg_last_error has the text) */
   DG_ENONPHYS = 4,      /* a kernel saw rho <= 0, p <= 0 or a NaN (from dg_sync) */
-  DG_EUNSUPPORTED = 5   /* valid request that this build does not implement      */
+  DG_EUNSUPPORTED = 5   /* valid request that this library does not implement    */
 } dg_status;
 
 #define DG_BC_PERIODIC 0
@@ -160,7 +160,7 @@ dg_status dg_set_state(dg_ctx* ctx, const double* U_dev);
 dg_status dg_get_state(const dg_ctx* ctx, double* U_dev);
 
 /* Ut = L(U) (paper Sec. 2.2 semi-discrete operator).  U and Ut must not overlap.
- * t is the physical time (no time-dependent terms in this build).            */
+ * t is the physical time (the operator has no time-dependent terms).       */
 dg_status dg_eval_rhs(dg_ctx* ctx, const double* U_dev, double* Ut_dev, double t);
 
 /* BR1 lifted gradients of (u, v, w, T) of U, layout above (FP64 contexts only). */
