@@ -136,39 +136,40 @@ def _leg(wl_name, r):
             "step_alg_gbs": r["step_alg_gbs"], "step_frac": r["step_alg_gbs"] / HBM_PEAK_GBS}
 
 
-def curved_alg_bytes(N: int = 7):
-    """Algorithmic bytes per DOF and stage of the curved-element kernels (FP64):
+def curved_alg_bytes(N: int = 7, mixed: bool = False):
+    """Algorithmic bytes per DOF and stage of the curved-element kernels:
     k_rhs_curv reads U 40, the neighbours' face fluxes 24 (6 (N+1)^2 faces x 4
-    values per element), G 40 (not on stage 1) and the metric terms 80 (J a^i_n
-    and 1/J), and writes G and U (80); k_face_flux_curv reads U 40 and the
-    metric terms of the face nodes only, and writes the face fluxes."""
+    values per element; FP32 in mixed precision), G 40 (not on stage 1) and the
+    metric terms 80 (J a^i_n and 1/J), and writes G and U (80);
+    k_face_flux_curv reads U 40 and the metric terms of the face nodes only,
+    and writes the face fluxes."""
     NP = N + 1
-    ff = 24.0 / NP * 8
+    ff = 24.0 / NP * (4 if mixed else 8)
     face_nodes = 2 * NP * NP + (N - 1) * 4 * N
     return {"face": 40 + 80.0 * face_nodes / NP ** 3 + ff, "rk": 40 + ff + 40 + 80 + 80,
             "rk_first": 40 + ff + 80 + 80}
 
 
-def run_curved(steps, warmup, flux=None):
-    """The Taylor-Green step on the warped (curved) N = 7, 32^3 mesh, FP64
-    (the workload's Kennedy-Gruber / Lax-Friedrichs pair unless `flux`)."""
+def run_curved(steps, warmup, flux=None, precision="fp64"):
+    """The Taylor-Green step on the warped (curved) N = 7, 32^3 mesh (the
+    workload's Kennedy-Gruber / Lax-Friedrichs pair unless `flux`)."""
     import torch
 
     from paper_2606_18927_amd import dgsem, workloads
     wl = workloads.WORKLOADS["tgv_n7_32x32x32_curved"]
     xi, _ = dgsem.lgl(wl.N)
     U, dt = workloads.make_state(wl, xi)
-    S = dgsem.solver_for(wl, flux=flux)
+    S = dgsem.solver_for(wl, flux=flux, precision=precision)
     S.set_state(torch.as_tensor(U.reshape(-1)).cuda())
     del U
     ms, lift_ms, rk_ms, n_lift, n_rk = time_steps(S, dt, steps, warmup)
     dof, stages = S.n_dof, steps * 5
-    b = curved_alg_bytes(wl.N)
+    b = curved_alg_bytes(wl.N, precision == "mixed")
     rk_bytes = dof * (b["rk"] * (stages - steps) + b["rk_first"] * steps) / stages
     rk_s = rk_ms / 1e3 / n_rk
     face_s = lift_ms / 1e3 / max(n_lift, 1)
     step_bytes = dof * (b["face"] * stages + b["rk"] * (stages - steps) + b["rk_first"] * steps)
-    out = {"workload": wl.name, "warp": wl.warp, "flux": flux or wl.flux,
+    out = {"workload": wl.name, "warp": wl.warp, "flux": flux or wl.flux, "precision": precision,
            "ns_per_dof_stage": ms * 1e6 / (dof * stages),
            "ms_per_step": ms / steps, "rk_kernel": "k_rhs_curv", "rk_kernel_ms": rk_ms / n_rk,
            "face_kernel_ms": lift_ms / max(n_lift, 1), "rk_bytes_per_launch": rk_bytes,
@@ -176,7 +177,8 @@ def run_curved(steps, warmup, flux=None):
            "face_kernel_gbs": dof * b["face"] / face_s / 1e9,
            "step_alg_bytes_per_dof": step_bytes / (dof * stages), "step_alg_gbs": step_bytes / (ms / 1e3) / 1e9,
            "step_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
-    traffic = counted_traffic(COUNTED_TRAFFIC_CURVED, TRAFFIC_SOURCES_CURVED) if flux is None else None
+    traffic = (counted_traffic(COUNTED_TRAFFIC_CURVED, TRAFFIC_SOURCES_CURVED)
+               if flux is None and precision == "fp64" else None)
     out["rk_traffic"] = traffic
     out["rk_traffic_over_algorithmic"] = None if traffic is None else traffic / rk_bytes
     del S
@@ -538,6 +540,11 @@ def main():
             curved["ec_roe"] = {k: cec[k] for k in ("ns_per_dof_stage", "ms_per_step", "rk_kernel_ms",
                                                      "face_kernel_ms", "step_frac")}
             print(f"[bench] curved ec_roe {cec['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
+                  flush=True)
+            cmx = run_curved(args.steps, args.warmup, precision="mixed")
+            curved["mixed"] = {k: cmx[k] for k in ("ns_per_dof_stage", "ms_per_step", "rk_kernel_ms",
+                                                   "face_kernel_ms", "rk_kernel_gbs", "step_frac")}
+            print(f"[bench] curved mixed {cmx['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
                   flush=True)
         except dgsem.DgsemError as e:
             curved = {"error": str(e)}

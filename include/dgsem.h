@@ -102,7 +102,8 @@ typedef struct {
                          or isothermal-wall ends (the wall normal is the face's
                          metric vector); faces may be NULL.  DG_FP64 with either
                          flux pair (the Roe flux along the face's unit normal,
-                         scaled by its length); no wall model, adjoint,
+                         scaled by its length), DG_MIXED with the
+                         Kennedy-Gruber pair; no wall model, adjoint,
                          lifting or kinetic-energy calls (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
                          makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;

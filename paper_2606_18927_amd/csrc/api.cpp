@@ -182,21 +182,21 @@ dg_status wall_model_stress(dg_ctx* c, const double* U) {
 // Kernels of one stage for the context's element kind.
 hipError_t face_flux_any(const dg_ctx* c, const dg::DevMesh& m, const dg::DevPhys& p, const dg::DevBasis& b,
                          const double* U) {
-  if (c->curvilinear) return dg::launch_face_flux_curv(c->N, m, p, b, U, static_cast<double*>(c->ffv), c->stream);
+  if (c->curvilinear) return dg::launch_face_flux_curv(c->N, c->phys.precision, m, p, b, U, c->ffv, c->stream);
   return dg::launch_face_flux(c->N, c->phys.precision, m, p, b, U, c->ffv, c->stream);
 }
 
 hipError_t rhs_any(const dg_ctx* c, const dg::DevMesh& m, const dg::DevPhys& p, const dg::DevBasis& b,
                    const double* U, double* Ut) {
   if (c->curvilinear)
-    return dg::launch_rhs_curv(c->N, m, p, b, U, static_cast<const double*>(c->ffv), Ut, c->dstatus, c->stream);
+    return dg::launch_rhs_curv(c->N, c->phys.precision, m, p, b, U, c->ffv, Ut, c->dstatus, c->stream);
   return dg::launch_rhs(c->N, c->phys.precision, m, p, b, U, c->ffv, Ut, c->dstatus, c->stream);
 }
 
 hipError_t rk_stage_any(const dg_ctx* c, const dg::DevMesh& m, const dg::DevPhys& p, const dg::DevBasis& b,
                         const double* U, double* U_out, const dg::Stage& st) {
   if (c->curvilinear)
-    return dg::launch_rk_stage_curv(c->N, m, p, b, U, static_cast<const double*>(c->ffv), c->G, U_out, st,
+    return dg::launch_rk_stage_curv(c->N, c->phys.precision, m, p, b, U, c->ffv, c->G, U_out, st,
                                     c->dstatus, c->stream);
   return dg::launch_rk_stage(c->N, c->phys.precision, m, p, b, U, c->ffv, c->G, U_out, st, c->dstatus,
                              c->stream);
@@ -337,7 +337,8 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
     if (!(mesh->T_wall > 0.0)) return DG_EINVAL;
   }
   if (curved) {
-    if (wall_model || phys->precision != DG_FP64) return DG_EUNSUPPORTED;
+    if (wall_model) return DG_EUNSUPPORTED;
+    if (phys->precision != DG_FP64 && phys->flux == DG_FLUX_EC_ROE) return DG_EUNSUPPORTED;
     const long long n3 = 3 * nE * nn;
     for (long long q = 0; q < n3; ++q)
       if (!std::isfinite(mesh->nodes[q])) return DG_EINVAL;

@@ -1,5 +1,5 @@
-// Split-form DGSEM on curvilinear hexahedra (FP64, structured meshes with
-// periodic or isothermal no-slip wall ends).
+// Split-form DGSEM on curvilinear hexahedra (FP64 or mixed precision,
+// structured meshes with periodic or isothermal no-slip wall ends).
 //
 // Geometry (the paper's production meshes are curved, Sec. 4): each element's
 // map is the degree-N interpolant of its node coordinates.  The metric terms
@@ -36,16 +36,15 @@ struct CurvCfg {
 
 // sum_m D[idx][m] f(node with the dir-coordinate replaced by m), f an LDS field
 // indexed i + NP (j + NP k)
-template <int N>
-__device__ inline double dline(const double* f, const double (*sD)[N + 2], int dir, int i, int j,
-                               int k) {
+template <int N, typename R>
+__device__ inline R dline(const R* f, const double (*sD)[N + 2], int dir, int i, int j, int k) {
   constexpr int NP = N + 1;
   const int idx = dir == 0 ? i : (dir == 1 ? j : k);
   const int base = dir == 0 ? NP * (j + NP * k) : (dir == 1 ? i + NP * NP * k : i + NP * j);
   const int step = dir == 0 ? 1 : (dir == 1 ? NP : NP * NP);
-  double a = 0.0;
+  R a = R(0);
 #pragma unroll
-  for (int m = 0; m < NP; ++m) a += sD[idx][m] * f[base + step * m];
+  for (int m = 0; m < NP; ++m) a += static_cast<R>(sD[idx][m]) * f[base + step * m];
   return a;
 }
 
@@ -183,9 +182,9 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __rest
 
 // Own-side contravariant viscous flux along metric vector M from the stress:
 // (sum_d M_d tau_0d, sum_d M_d tau_1d, sum_d M_d tau_2d, u . (those) + M . qT)
-__device__ inline void contra_viscous(double u, double v, double w, const double tau[6],
-                                      const double qT[3], double M0, double M1, double M2,
-                                      double f[4]) {
+template <typename R>
+__device__ inline void contra_viscous(R u, R v, R w, const R tau[6], const R qT[3], R M0, R M1, R M2,
+                                      R f[4]) {
   f[0] = M0 * tau[0] + M1 * tau[3] + M2 * tau[4];
   f[1] = M0 * tau[3] + M1 * tau[1] + M2 * tau[5];
   f[2] = M0 * tau[4] + M1 * tau[5] + M2 * tau[2];
@@ -193,9 +192,9 @@ __device__ inline void contra_viscous(double u, double v, double w, const double
 }
 
 // Stress (t00, t11, t22, t01, t02, t12) and heat flux of physical gradients g[3 q + d]
-__device__ inline void stress64(const double g[12], double mu, double kappa, double tau[6],
-                                double qT[3]) {
-  const double dd = (2.0 / 3.0) * (g[0] + g[4] + g[8]);
+template <typename R>
+__device__ inline void stress64(const R g[12], R mu, R kappa, R tau[6], R qT[3]) {
+  const R dd = R(2.0 / 3.0) * (g[0] + g[4] + g[8]);
   tau[0] = mu * (g[0] + g[0] - dd);
   tau[1] = mu * (g[4] + g[4] - dd);
   tau[2] = mu * (g[8] + g[8] - dd);
@@ -211,16 +210,16 @@ __device__ inline void stress64(const double g[12], double mu, double kappa, dou
 // derivatives plus the lifting terms of the faces the node lies on, then
 // grad q = (1/J) sum_r J a^r gxi_r.  sq[c] are LDS fields of q; corr[f][c][ab]
 // the lifting terms (q* - q)(+-1/w) of face f.
-template <int N>
-__device__ inline void curv_gradients(const double* const sq[4], const double (*sD)[N + 2],
-                                      const double (*corr)[4][(N + 1) * (N + 1)], int i, int j, int k,
-                                      const double Ja[9], double invJ, double g[12]) {
+template <int N, typename R>
+__device__ inline void curv_gradients(const R* const sq[4], const double (*sD)[N + 2],
+                                      const R (*corr)[4][(N + 1) * (N + 1)], int i, int j, int k,
+                                      const R Ja[9], R invJ, R g[12]) {
   constexpr int NP = N + 1;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    double gx[3];
+    R gx[3];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) gx[r] = dline<N>(sq[c], sD, r, i, j, k);
+    for (int r = 0; r < 3; ++r) gx[r] = dline<N, R>(sq[c], sD, r, i, j, k);
     if (i == 0) gx[0] += corr[0][c][j + NP * k];
     if (i == N) gx[0] += corr[1][c][j + NP * k];
     if (j == 0) gx[1] += corr[2][c][i + NP * k];
@@ -240,9 +239,10 @@ __device__ inline void load_geo(const double* geo, long long stride, long long i
 }
 
 // ---------------------------------------------------------- face viscous flux
-template <int N>
+// (R = float in mixed precision: the fluxes are formed in FP64 and stored in FP32)
+template <int N, typename R>
 __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double* __restrict__ U,
-                                                                  double* __restrict__ ffv, DevMesh mesh,
+                                                                  R* __restrict__ ffv, DevMesh mesh,
                                                                   DevPhys ph, DevBasis basis) {
   using C = CurvCfg<N>;
   constexpr int NP = C::NP, NF = C::NF, NN = C::NN;
@@ -300,12 +300,12 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
   load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
   const double* const q[4] = {sq[0], sq[1], sq[2], sq[3]};
   double g[12];
-  curv_gradients<N>(q, sD, corr, i, j, k, Ja, invJ, g);
+  curv_gradients<N, double>(q, sD, corr, i, j, k, Ja, invJ, g);
   const double r = viscosity_ratio(ph, sq[3][tid]);
   double tau[6], qT[3];
-  stress64(g, ph.mu * r, ph.kappa * r, tau, qT);
+  stress64<double>(g, ph.mu * r, ph.kappa * r, tau, qT);
   const double u = sq[0][tid], v = sq[1][tid], w = sq[2][tid];
-  double* out = ffv + e * (6 * 4 * NF);
+  R* out = ffv + e * (6 * 4 * NF);
   double f[4];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -313,9 +313,9 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
     if (idx != 0 && idx != N) continue;
     const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
     const int fi = 2 * d + (idx == N ? 1 : 0);
-    contra_viscous(u, v, w, tau, qT, Ja[3 * d], Ja[3 * d + 1], Ja[3 * d + 2], f);
+    contra_viscous<double>(u, v, w, tau, qT, Ja[3 * d], Ja[3 * d + 1], Ja[3 * d + 2], f);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) out[(fi * 4 + c) * NF + ab] = f[c];
+    for (int c = 0; c < 4; ++c) out[(fi * 4 + c) * NF + ab] = static_cast<R>(f[c]);
   }
 }
 
@@ -324,24 +324,33 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
 // entropy-conserving ones are bounded for three: at 128 they spilled 46-58
 // values per lane, and at degree 7 one workgroup per CU without spills is 17 %
 // faster than two with them.
-template <int N, bool RK, bool VISC, bool EC>
+// R = float: mixed precision (Kennedy-Gruber pair only): the LDS fields,
+// gradients, metric terms of the sweeps and line sums in FP32, with p, e and T
+// relative to the element's first node; primitive recovery, lifting
+// corrections, surface fluxes, 1/J scaling and the RK update in FP64.  The
+// reference pressure's share of the momentum sums is the discrete divergence
+// of the metric terms (zero by the metric identities) and is dropped; the
+// energy's, e_ref sum D (rho U~)# + p_ref sum D U~#, is added back in FP64.
+template <int N, typename R, bool RK, bool VISC, bool EC>
 __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(EC ? 3 : 4))) void k_rhs_curv(
-    const double* __restrict__ U, const double* __restrict__ ffv, double* __restrict__ out,
+    const double* __restrict__ U, const R* __restrict__ ffv, double* __restrict__ out,
     double* __restrict__ U_out, DevMesh mesh, DevPhys ph, DevBasis basis, Stage st,
     int* __restrict__ status) {
   using C = CurvCfg<N>;
   constexpr int NP = C::NP, NF = C::NF, NN = C::NN;
+  constexpr bool MIXED = sizeof(R) == sizeof(float);
+  static_assert(!(EC && MIXED), "the entropy-conserving pair on curved elements is FP64 only");
   __shared__ double sD[NP][N + 2];
-  __shared__ double sp[6][NN];            // rho, u, v, w, p, e
+  __shared__ R sp[6][NN];                 // rho, u, v, w, p, e (p, e relative to the reference if MIXED)
   __shared__ double sX[6][5][NF];         // own viscous face flux, then surface terms
   // phase-shared regions: (T, lifting terms) until the gradients are formed,
   // (viscous flux, metric of the sweep direction) in the sweeps
   constexpr int R1 = NN + 6 * 4 * NF, R2 = 4 * NN + 3 * NN;
-  __shared__ double sbuf[R1 > R2 ? R1 : R2];
-  double* sT = sbuf;
-  double(*corr)[4][NF] = reinterpret_cast<double(*)[4][NF]>(sbuf + NN);
-  double(*sfv)[NN] = reinterpret_cast<double(*)[NN]>(sbuf);
-  double(*sM)[NN] = reinterpret_cast<double(*)[NN]>(sbuf + 4 * NN);
+  __shared__ R sbuf[R1 > R2 ? R1 : R2];
+  R* sT = sbuf;
+  R(*corr)[4][NF] = reinterpret_cast<R(*)[4][NF]>(sbuf + NN);
+  R(*sfv)[NN] = reinterpret_cast<R(*)[NN]>(sbuf);
+  R(*sM)[NN] = reinterpret_cast<R(*)[NN]>(sbuf + 4 * NN);
 
   const int tid = threadIdx.x;
   const long long nE = mesh.nE;
@@ -357,26 +366,37 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   // P1: own state; face lanes fetch the neighbour's face node (registers are
   // the limit of this kernel: metric terms, the neighbour's state and the own
   // primitives are fetched again where they are used, from L2 and LDS)
+  double p_ref = 0.0, e_ref = 0.0, T_ref = 0.0;  // mixed precision: the element's first node
   if (active) {
     double u0[5];
     load_state(U, stride, e * NN + tid, u0);
     const Prim P = primitives(u0, ph);
     if (!(P.rho > 0.0) || !(P.p > 0.0)) status[0] = 1;
-    sp[0][tid] = P.rho;
-    sp[1][tid] = P.u;
-    sp[2][tid] = P.v;
-    sp[3][tid] = P.w;
-    sp[4][tid] = EC ? 0.5 * P.rho / P.p : P.p;
-    sp[5][tid] = EC ? P.u * P.u + P.v * P.v + P.w * P.w : P.e;
-    if (VISC) sT[tid] = P.T;
+    if (MIXED && ph.mixed_ref) {
+      double s0[5];
+      load_state(U, stride, e * NN, s0);
+      const Prim P0 = primitives(s0, ph);
+      p_ref = P0.p;
+      e_ref = P0.e;
+      T_ref = P0.T;
+    }
+    sp[0][tid] = static_cast<R>(P.rho);
+    sp[1][tid] = static_cast<R>(P.u);
+    sp[2][tid] = static_cast<R>(P.v);
+    sp[3][tid] = static_cast<R>(P.w);
+    sp[4][tid] = static_cast<R>(EC ? 0.5 * P.rho / P.p : P.p - p_ref);
+    sp[5][tid] = static_cast<R>(EC ? P.u * P.u + P.v * P.v + P.w * P.w : P.e - e_ref);
+    if (VISC) sT[tid] = static_cast<R>(P.T - T_ref);
   }
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+  double so[5] = {1.0, 0.0, 0.0, 0.0, 1.0};  // own face node (mixed precision)
   bool fwall1 = true;  // the face task's face is a wall (P1b)
   if (VISC && face_lane) {
     const FaceTask<N> ft(tid);
     const long long nb = neighbour(mesh, ex, ey, ez, ft.d, ft.up);
     fwall1 = nb < 0;
     if (!fwall1) load_state(U, stride, nb * NN + ft.nb_node(), sn);
+    if (MIXED) load_state(U, stride, e * NN + ft.own_node(), so);
   }
   __syncthreads();
 
@@ -385,7 +405,19 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     if (face_lane) {
       const FaceTask<N> ft(tid);
       const int lo = ft.own_node();
-      const double qo[4] = {sp[1][lo], sp[2][lo], sp[3][lo], sT[lo]};
+      double qo[4];
+      if constexpr (MIXED) {
+        const Prim Po = primitives(so, ph);
+        qo[0] = Po.u;
+        qo[1] = Po.v;
+        qo[2] = Po.w;
+        qo[3] = Po.T;
+      } else {
+        qo[0] = sp[1][lo];
+        qo[1] = sp[2][lo];
+        qo[2] = sp[3][lo];
+        qo[3] = sT[lo];
+      }
       double qs[4] = {0.0, 0.0, 0.0, mesh.T_wall};  // isothermal no-slip wall
       if (!fwall1) {
         const Prim Pn = primitives(sn, ph);
@@ -396,22 +428,25 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       }
       const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (qs[c] - qo[c]) * sc;
+      for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = static_cast<R>((qs[c] - qo[c]) * sc);
     }
     __syncthreads();
   }
 
   // P2: gradients, stress and heat flux
-  double tau[6] = {0, 0, 0, 0, 0, 0}, qT[3] = {0, 0, 0};
+  R tau[6] = {0, 0, 0, 0, 0, 0}, qT[3] = {0, 0, 0};
   if (VISC) {
     if (active) {
       double Ja[9], invJ;
       load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
-      const double* const q[4] = {sp[1], sp[2], sp[3], sT};
-      double g[12];
-      curv_gradients<N>(q, sD, corr, i, j, k, Ja, invJ, g);
-      const double r = viscosity_ratio(ph, sT[tid]);
-      stress64(g, ph.mu * r, ph.kappa * r, tau, qT);
+      R Jr[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) Jr[c] = static_cast<R>(Ja[c]);
+      const R* const q[4] = {sp[1], sp[2], sp[3], sT};
+      R g[12];
+      curv_gradients<N, R>(q, sD, corr, i, j, k, Jr, static_cast<R>(invJ), g);
+      const double r = viscosity_ratio(ph, static_cast<double>(sT[tid]) + T_ref);
+      stress64<R>(g, static_cast<R>(ph.mu * r), static_cast<R>(ph.kappa * r), tau, qT);
     }
     __syncthreads();
   }
@@ -422,20 +457,20 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   for (int d = 0; d < 3; ++d) {
     const int idx = d == 0 ? i : (d == 1 ? j : k);
     const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
-    double M0 = 0.0, M1 = 0.0, M2 = 0.0, A[6] = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
+    R M0 = 0, M1 = 0, M2 = 0, A[6] = {1, 0, 0, 0, 1, 1};
     if (active) {
       const long long gi = e * NN + tid;
-      M0 = mesh.geo[(3 * d) * stride + gi];
-      M1 = mesh.geo[(3 * d + 1) * stride + gi];
-      M2 = mesh.geo[(3 * d + 2) * stride + gi];
+      M0 = static_cast<R>(mesh.geo[(3 * d) * stride + gi]);
+      M1 = static_cast<R>(mesh.geo[(3 * d + 1) * stride + gi]);
+      M2 = static_cast<R>(mesh.geo[(3 * d + 2) * stride + gi]);
 #pragma unroll
       for (int c = 0; c < 6; ++c) A[c] = sp[c][tid];
       sM[0][tid] = M0;
       sM[1][tid] = M1;
       sM[2][tid] = M2;
       if (VISC) {
-        double f[4];
-        contra_viscous(A[1], A[2], A[3], tau, qT, M0, M1, M2, f);
+        R f[4];
+        contra_viscous<R>(A[1], A[2], A[3], tau, qT, M0, M1, M2, f);
 #pragma unroll
         for (int c = 0; c < 4; ++c) sfv[c][tid] = f[c];
         if (idx == 0 || idx == N) {
@@ -449,7 +484,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     if (active) {
       const int base = d == 0 ? NP * (j + NP * k) : (d == 1 ? i + NF * k : i + NP * j);
       const int step = d == 0 ? 1 : (d == 1 ? NP : NF);
-      double ac[5] = {0, 0, 0, 0, 0}, av[4] = {0, 0, 0, 0};
+      R ac[5] = {0, 0, 0, 0, 0}, av[4] = {0, 0, 0, 0}, du = 0;
       if constexpr (EC) {
         // not unrolled: the pair flux is long, and unrolled copies keep too
         // many values live
@@ -472,30 +507,34 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
           const int nm = base + step * m;
-          const double Dm = sD[idx][m];
-          const double m0 = 0.5 * (M0 + sM[0][nm]), m1 = 0.5 * (M1 + sM[1][nm]), m2 = 0.5 * (M2 + sM[2][nm]);
-          const double rho = 0.5 * (A[0] + sp[0][nm]);
-          const double uu = 0.5 * (A[1] + sp[1][nm]);
-          const double vv = 0.5 * (A[2] + sp[2][nm]);
-          const double ww = 0.5 * (A[3] + sp[3][nm]);
-          const double pp = 0.5 * (A[4] + sp[4][nm]);
-          const double ee = 0.5 * (A[5] + sp[5][nm]);
-          const double Uc = uu * m0 + vv * m1 + ww * m2;
-          const double mass = rho * Uc;
+          const R Dm = static_cast<R>(sD[idx][m]);
+          const R h = R(0.5);
+          const R m0 = h * (M0 + sM[0][nm]), m1 = h * (M1 + sM[1][nm]), m2 = h * (M2 + sM[2][nm]);
+          const R rho = h * (A[0] + sp[0][nm]);
+          const R uu = h * (A[1] + sp[1][nm]);
+          const R vv = h * (A[2] + sp[2][nm]);
+          const R ww = h * (A[3] + sp[3][nm]);
+          const R pp = h * (A[4] + sp[4][nm]);
+          const R ee = h * (A[5] + sp[5][nm]);
+          const R Uc = uu * m0 + vv * m1 + ww * m2;
+          const R mass = rho * Uc;
           ac[0] += Dm * mass;
           ac[1] += Dm * (mass * uu + pp * m0);
           ac[2] += Dm * (mass * vv + pp * m1);
           ac[3] += Dm * (mass * ww + pp * m2);
           ac[4] += Dm * (mass * ee + pp * Uc);
+          if (MIXED) du += Dm * Uc;
           if (VISC) {
 #pragma unroll
             for (int c = 0; c < 4; ++c) av[c] += Dm * sfv[c][nm];
           }
         }
       }
-      ut[0] -= 2.0 * ac[0];
+      ut[0] -= 2.0 * static_cast<double>(ac[0]);
 #pragma unroll
-      for (int c = 0; c < 4; ++c) ut[1 + c] -= 2.0 * ac[1 + c] - av[c];
+      for (int c = 0; c < 4; ++c) ut[1 + c] -= 2.0 * static_cast<double>(ac[1 + c]) - static_cast<double>(av[c]);
+      if (MIXED)
+        ut[4] -= 2.0 * (e_ref * static_cast<double>(ac[0]) + p_ref * static_cast<double>(du));
     }
     __syncthreads();
   }
@@ -563,7 +602,16 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
         }
       }
     } else {
-      const double Ao[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
+      double Ao[6];
+      if constexpr (MIXED) {  // the own face node in FP64, from U
+        double s5[5];
+        load_state(U, stride, e * NN + lo, s5);
+        const Prim Po = primitives(s5, ph);
+        Ao[0] = Po.rho; Ao[1] = Po.u; Ao[2] = Po.v; Ao[3] = Po.w; Ao[4] = Po.p; Ao[5] = Po.e;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Ao[c] = sp[c][lo];
+      }
       const double An[6] = {Pn.rho, Pn.u, Pn.v, Pn.w, Pn.p, Pn.e};
       const double so[5] = {Ao[0], Ao[0] * Ao[1], Ao[0] * Ao[2], Ao[0] * Ao[3], Ao[0] * Ao[5]};
       vo[0] = Ao[1];
@@ -615,9 +663,9 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
         for (int c = 0; c < 3; ++c) fvs[c] = fvo[c];
         fvs[3] = fvo[3] - (vo[0] * fvo[0] + vo[1] * fvo[1] + vo[2] * fvo[2]);
       } else {
-        const double* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
+        const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fvs[c] = 0.5 * (fvo[c] + src[c * NF]);
+        for (int c = 0; c < 4; ++c) fvs[c] = 0.5 * (fvo[c] + static_cast<double>(src[c * NF]));
       }
     }
     const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
@@ -674,34 +722,52 @@ hipError_t metrics_n(const double* X, double* geo, const DevBasis& b, long long 
   return hipGetLastError();
 }
 
-template <int N>
+template <int N, typename R>
 hipError_t face_flux_curv_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
-                            double* ffv, hipStream_t s) {
-  hipLaunchKernelGGL((k_face_flux_curv<N>), dim3(static_cast<unsigned>(m.nE)), dim3(CurvCfg<N>::BS), 0, s, U,
-                     ffv, m, p, b);
+                            void* ffv, hipStream_t s) {
+  hipLaunchKernelGGL((k_face_flux_curv<N, R>), dim3(static_cast<unsigned>(m.nE)), dim3(CurvCfg<N>::BS), 0, s,
+                     U, static_cast<R*>(ffv), m, p, b);
   return hipGetLastError();
 }
 
-template <int N, bool RK>
+template <int N, typename R, bool RK>
 hipError_t rhs_curv_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
-                      const double* ffv, double* out, double* U_out, const Stage& st, int* status,
+                      const void* ffv_, double* out, double* U_out, const Stage& st, int* status,
                       hipStream_t s) {
   const dim3 grid(static_cast<unsigned>(m.nE)), block(CurvCfg<N>::BS);
-  if (p.ec) {
-    if (p.viscous)
-      hipLaunchKernelGGL((k_rhs_curv<N, RK, true, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
-                         status);
-    else
-      hipLaunchKernelGGL((k_rhs_curv<N, RK, false, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
-                         status);
-  } else if (p.viscous) {
-    hipLaunchKernelGGL((k_rhs_curv<N, RK, true, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
-                       status);
+  const R* ffv = static_cast<const R*>(ffv_);
+  if constexpr (sizeof(R) == sizeof(double)) {
+    if (p.ec) {
+      if (p.viscous)
+        hipLaunchKernelGGL((k_rhs_curv<N, R, RK, true, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b,
+                           st, status);
+      else
+        hipLaunchKernelGGL((k_rhs_curv<N, R, RK, false, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b,
+                           st, status);
+      return hipGetLastError();
+    }
   } else {
-    hipLaunchKernelGGL((k_rhs_curv<N, RK, false, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
-                       status);
+    if (p.ec) return hipErrorInvalidValue;  // rejected at init: FP64 only on curved elements
   }
+  if (p.viscous)
+    hipLaunchKernelGGL((k_rhs_curv<N, R, RK, true, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
+                       status);
+  else
+    hipLaunchKernelGGL((k_rhs_curv<N, R, RK, false, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,
+                       status);
   return hipGetLastError();
+}
+
+template <typename R, bool RK>
+hipError_t rhs_curv_dispatch(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b, const double* U,
+                             const void* ffv, double* out, double* U_out, const Stage& st, int* status,
+                             hipStream_t s) {
+  switch (N) {
+    case 3: return rhs_curv_n<3, R, RK>(m, p, b, U, ffv, out, U_out, st, status, s);
+    case 5: return rhs_curv_n<5, R, RK>(m, p, b, U, ffv, out, U_out, st, status, s);
+    case 7: return rhs_curv_n<7, R, RK>(m, p, b, U, ffv, out, U_out, st, status, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -716,36 +782,31 @@ hipError_t launch_metrics(int N, const double* X, double* geo, const DevBasis& b
   }
 }
 
-hipError_t launch_face_flux_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                                 const double* U, double* ffv, hipStream_t s) {
+hipError_t launch_face_flux_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                 const double* U, void* ffv, hipStream_t s) {
+  const bool f32 = precision != DG_FP64;
   switch (N) {
-    case 3: return face_flux_curv_n<3>(m, p, b, U, ffv, s);
-    case 5: return face_flux_curv_n<5>(m, p, b, U, ffv, s);
-    case 7: return face_flux_curv_n<7>(m, p, b, U, ffv, s);
+    case 3: return f32 ? face_flux_curv_n<3, float>(m, p, b, U, ffv, s) : face_flux_curv_n<3, double>(m, p, b, U, ffv, s);
+    case 5: return f32 ? face_flux_curv_n<5, float>(m, p, b, U, ffv, s) : face_flux_curv_n<5, double>(m, p, b, U, ffv, s);
+    case 7: return f32 ? face_flux_curv_n<7, float>(m, p, b, U, ffv, s) : face_flux_curv_n<7, double>(m, p, b, U, ffv, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_rhs_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                           const double* U, const double* ffv, double* Ut, int* status, hipStream_t s) {
+hipError_t launch_rhs_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                           const double* U, const void* ffv, double* Ut, int* status, hipStream_t s) {
   const Stage st{0.0, 0.0, 0.0, 0};
-  switch (N) {
-    case 3: return rhs_curv_n<3, false>(m, p, b, U, ffv, Ut, nullptr, st, status, s);
-    case 5: return rhs_curv_n<5, false>(m, p, b, U, ffv, Ut, nullptr, st, status, s);
-    case 7: return rhs_curv_n<7, false>(m, p, b, U, ffv, Ut, nullptr, st, status, s);
-    default: return hipErrorInvalidValue;
-  }
+  return precision != DG_FP64
+             ? rhs_curv_dispatch<float, false>(N, m, p, b, U, ffv, Ut, nullptr, st, status, s)
+             : rhs_curv_dispatch<double, false>(N, m, p, b, U, ffv, Ut, nullptr, st, status, s);
 }
 
-hipError_t launch_rk_stage_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                                const double* U, const double* ffv, double* G, double* U_out,
+hipError_t launch_rk_stage_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                const double* U, const void* ffv, double* G, double* U_out,
                                 const Stage& st, int* status, hipStream_t s) {
-  switch (N) {
-    case 3: return rhs_curv_n<3, true>(m, p, b, U, ffv, G, U_out, st, status, s);
-    case 5: return rhs_curv_n<5, true>(m, p, b, U, ffv, G, U_out, st, status, s);
-    case 7: return rhs_curv_n<7, true>(m, p, b, U, ffv, G, U_out, st, status, s);
-    default: return hipErrorInvalidValue;
-  }
+  return precision != DG_FP64
+             ? rhs_curv_dispatch<float, true>(N, m, p, b, U, ffv, G, U_out, st, status, s)
+             : rhs_curv_dispatch<double, true>(N, m, p, b, U, ffv, G, U_out, st, status, s);
 }
 
 }  // namespace dg

@@ -78,17 +78,18 @@ hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBa
 // callers that capture the stream into a graph).
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
-// Curvilinear hexahedra (curv_kernels.hip, FP64): metric terms from the node
+// Curvilinear hexahedra (curv_kernels.hip): metric terms from the node
 // coordinates X[n][e][node] (status[0] = 1 where J <= 0), and the operator
-// (face viscous fluxes double*, one RK stage or the right-hand side alone).
+// (face viscous fluxes double*, or float* unless precision is DG_FP64; one RK
+// stage or the right-hand side alone).
 hipError_t launch_metrics(int N, const double* X, double* geo, const DevBasis& b, long long nE,
                           int* status, hipStream_t s);
-hipError_t launch_face_flux_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                                 const double* U, double* ffv, hipStream_t s);
-hipError_t launch_rhs_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                           const double* U, const double* ffv, double* Ut, int* status, hipStream_t s);
-hipError_t launch_rk_stage_curv(int N, const DevMesh& m, const DevPhys& p, const DevBasis& b,
-                                const double* U, const double* ffv, double* G, double* U_out,
+hipError_t launch_face_flux_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                 const double* U, void* ffv, hipStream_t s);
+hipError_t launch_rhs_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                           const double* U, const void* ffv, double* Ut, int* status, hipStream_t s);
+hipError_t launch_rk_stage_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
+                                const double* U, const void* ffv, double* G, double* U_out,
                                 const Stage& st, int* status, hipStream_t s);
 
 // Wall-stress model: number of wall faces of the mesh, and the kernel (one

@@ -39,12 +39,12 @@ hipError_t launch_triad(const double*, const double*, double, double*, long long
 hipError_t launch_metrics(int, const double*, double*, const DevBasis&, long long, int*, hipStream_t) {
   reached("metrics");
 }
-hipError_t launch_face_flux_curv(int, const DevMesh&, const DevPhys&, const DevBasis&, const double*, double*,
+hipError_t launch_face_flux_curv(int, int, const DevMesh&, const DevPhys&, const DevBasis&, const double*, void*,
                                  hipStream_t) { reached("face_flux_curv"); }
-hipError_t launch_rhs_curv(int, const DevMesh&, const DevPhys&, const DevBasis&, const double*, const double*,
+hipError_t launch_rhs_curv(int, int, const DevMesh&, const DevPhys&, const DevBasis&, const double*, const void*,
                            double*, int*, hipStream_t) { reached("rhs_curv"); }
-hipError_t launch_rk_stage_curv(int, const DevMesh&, const DevPhys&, const DevBasis&, const double*,
-                                const double*, double*, double*, const Stage&, int*, hipStream_t) {
+hipError_t launch_rk_stage_curv(int, int, const DevMesh&, const DevPhys&, const DevBasis&, const double*,
+                                const void*, double*, double*, const Stage&, int*, hipStream_t) {
   reached("rk_stage_curv");
 }
 }  // namespace dg

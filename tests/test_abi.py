@@ -193,7 +193,11 @@ def test_curved_mesh_validation(L):
     L.dg_free(ctx)
     nd = 8 * 64
     assert size.value >= plain.value + 10 * nd * 8  # metric terms: 10 values per DOF
-    for bad, code in ((dict(precision=1), dgsem.DG_EUNSUPPORTED),):
+    d, keep = desc()
+    st, ctx = _init(L, d, _phys(precision=1))  # mixed precision with the Kennedy-Gruber pair
+    assert st == dgsem.DG_OK
+    L.dg_free(ctx)
+    for bad, code in ((dict(precision=1, flux=1), dgsem.DG_EUNSUPPORTED),):
         d, keep = desc()
         assert _init(L, d, _phys(**bad))[0] == code, bad
     d, keep = desc(bc=(0, 1, 0))  # isothermal walls are fine

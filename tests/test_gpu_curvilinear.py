@@ -322,7 +322,7 @@ def test_curved_rejected_combinations():
     need_gpu()
     N = 3
     X = _warped(N, (2, 2, 2), 0.05)
-    for kw in (dict(precision="mixed"),):
+    for kw in (dict(precision="mixed", flux="ec_roe"),):
         with pytest.raises(dgsem.DgsemError) as ei:
             _solver(N, X, GAS, **kw)
         assert ei.value.status == dgsem.DG_EUNSUPPORTED
