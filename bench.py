@@ -57,15 +57,18 @@ STORED_GRADIENT_BYTES_PER_DOF = 392.0
 
 # HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
 # counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
-# 128 x 14,216,440.4 TCC_EA0_RDREQ_128B + 64 x 2,529.1 RDREQ_64B, writes
+# 128 x 14,212,096.9 TCC_EA0_RDREQ_128B + 64 x 2,529.0 RDREQ_64B, writes
 # WRITE_SIZE 1,310,720 KiB.  Valid only for the kernel sources it was counted
 # on; reported as null once they change.
-COUNTED_TRAFFIC = {"sources_sha256_prefix": "8f9bdc31aa34ecaa", "bytes_per_launch": 3162043515.0}
+COUNTED_TRAFFIC = {"sources_sha256_prefix": "dfaa36e09b1578e5", "bytes_per_launch": 3161487541.0}
 TRAFFIC_SOURCES = ("fwd_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
-# The same for k_rhs_curv<7,true,true,false> on the curved workload
+# The same for k_rhs_curv<7,double,true,true,false> on the curved workload
 # (profiles/k_rhs_curv_k_face_flux_curv_tgv_n7_32x32x32_curved.md): reads
-# 128 x 46,930,789.5 RDREQ_128B + 64 x 1,966.6 RDREQ_64B, writes 1,310,720 KiB.
-COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "fbf41dc1c665f986", "bytes_per_launch": 7349444203.0}
+# 128 x 46,462,404.1 RDREQ_128B + 64 x 2,012.4 RDREQ_64B, writes 1,310,720 KiB;
+# and for its mixed-precision instance k_rhs_curv<7,float,true,true,false>:
+# reads 128 x 42,520,703.7 RDREQ_128B + 64 x 8,480.2 RDREQ_64B, same writes.
+COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "4c5d4294668cc649", "bytes_per_launch": 7289493794.0}
+COUNTED_TRAFFIC_CURVED_MIXED = {"sources_sha256_prefix": "4c5d4294668cc649", "bytes_per_launch": 6785370082.0}
 TRAFFIC_SOURCES_CURVED = ("curv_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 
 
@@ -177,8 +180,8 @@ def run_curved(steps, warmup, flux=None, precision="fp64"):
            "face_kernel_gbs": dof * b["face"] / face_s / 1e9,
            "step_alg_bytes_per_dof": step_bytes / (dof * stages), "step_alg_gbs": step_bytes / (ms / 1e3) / 1e9,
            "step_frac": step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
-    traffic = (counted_traffic(COUNTED_TRAFFIC_CURVED, TRAFFIC_SOURCES_CURVED)
-               if flux is None and precision == "fp64" else None)
+    counted = COUNTED_TRAFFIC_CURVED if precision == "fp64" else COUNTED_TRAFFIC_CURVED_MIXED
+    traffic = counted_traffic(counted, TRAFFIC_SOURCES_CURVED) if flux is None else None
     out["rk_traffic"] = traffic
     out["rk_traffic_over_algorithmic"] = None if traffic is None else traffic / rk_bytes
     del S
@@ -543,7 +546,8 @@ def main():
                   flush=True)
             cmx = run_curved(args.steps, args.warmup, precision="mixed")
             curved["mixed"] = {k: cmx[k] for k in ("ns_per_dof_stage", "ms_per_step", "rk_kernel_ms",
-                                                   "face_kernel_ms", "rk_kernel_gbs", "step_frac")}
+                                                   "face_kernel_ms", "rk_kernel_gbs", "step_frac", "rk_traffic",
+                                                   "rk_traffic_over_algorithmic")}
             print(f"[bench] curved mixed {cmx['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
                   flush=True)
         except dgsem.DgsemError as e:
