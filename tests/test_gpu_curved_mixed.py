@@ -3,7 +3,8 @@
 The Kennedy-Gruber pair on curved elements with the LDS fields, gradients,
 sweep metrics and line sums in FP32 (p, e and T relative to each element's
 first node) and the primitive recovery, lifting corrections, surface fluxes,
-1/J scaling and RK update in FP64.  Bound as for the other mixed paths:
+1/J scaling and RK update in FP64 (Navier-Stokes, Euler and the central
+flux; periodic boxes and wavy walls).  Bound as for the other mixed paths:
 relative L2 error per conserved variable <= 1e-4 for Ut against the FP64
 oracle and for the change of the state over RK steps against the FP64 path.
 """
@@ -17,7 +18,7 @@ from oracle.physics import Gas
 from paper_2606_18927_amd import dgsem, workloads
 
 from _cases import random_state
-from _gpu import need_gpu, oracle_gas, rel_l2, say, state, to_dev
+from _gpu import need_gpu, oracle_gas, say, state, to_dev
 
 pytestmark = pytest.mark.gpu
 BOUND = 1e-4
@@ -42,23 +43,26 @@ def _table(name, got, ref, momentum_norm=False):
     return rel
 
 
-@pytest.mark.parametrize("N,n,amp,suth", [
-    (3, (2, 3, 2), 0.08, False),
-    (5, (2, 2, 3), 0.05, False),
-    (7, (2, 2, 2), 0.05, False),
-    (5, (2, 2, 2), 0.08, True),
+@pytest.mark.parametrize("N,n,amp,suth,viscous,central", [
+    (3, (2, 3, 2), 0.08, False, True, False),
+    (5, (2, 2, 3), 0.05, False, True, False),
+    (7, (2, 2, 2), 0.05, False, True, False),
+    (5, (2, 2, 2), 0.08, True, True, False),
+    (3, (3, 2, 2), 0.08, False, False, False),
+    (5, (2, 2, 2), 0.08, False, True, True),
 ])
-def test_curved_mixed_rhs_against_fp64_oracle(N, n, amp, suth):
+def test_curved_mixed_rhs_against_fp64_oracle(N, n, amp, suth, viscous, central):
     need_gpu()
+    say("curved mixed rhs", N, n, amp, suth, viscous, central)
     X = workloads.warped_nodes(dgsem.lgl(N)[0], n, amp=amp)
     mesh = cv.CurvMesh(N, torch.as_tensor(X))
     g = Gas(gamma=1.4, R=1.0, mu=0.02, Pr=0.72, sutherland=True, T_ref=1.0, S=0.4) if suth else GAS
     U = random_state(mesh, g.gamma, g.R, np.random.default_rng(40 + N)).numpy()
-    S = _solver(N, X, g)
+    S = _solver(N, X, g, viscous=viscous, central_only=central)
     got = S.eval_rhs(to_dev(U)).cpu().numpy()
     S.sync()
-    ref = cv.rhs(torch.as_tensor(U), mesh, g).numpy()
-    assert np.all(_table(f"curved mixed N={N} suth={suth}", got, ref) < BOUND)
+    ref = cv.rhs(torch.as_tensor(U), mesh, g, viscous=viscous, central_only=central).numpy()
+    assert np.all(_table(f"curved mixed N={N}", got, ref) < BOUND)
 
 
 def test_curved_mixed_wavy_channel_against_fp64_oracle():

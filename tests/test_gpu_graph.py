@@ -2,7 +2,7 @@
 against the same steps launched eagerly (GPU).
 
 The graph holds the same kernels in the same order, so every replay must give
-bitwise the state that dg_rk_step gives.  Each test replays several times,
+bitwise the state that dg_rk_step gives (axis-aligned and curved meshes).  Each test replays several times,
 with eager GPU work and synchronisations between the replays, and checks
 every replay.
 """
@@ -21,6 +21,8 @@ CASES = [
     ("tgv_n3_4x4x4 fp64", lambda: workloads.WORKLOADS["tgv_n3_4x4x4"], "fp64"),
     ("channel_n5 mixed", lambda: custom("channel", 5, (2, 3, 2), seed=workloads.CHANNEL_SEED), "mixed"),
     ("tgv_n3 ec_roe", lambda: custom("tgv", 3, (3, 2, 2), noise=0.01, seed=4, flux="ec_roe"), "fp64"),
+    ("tgv_n3 curved fp64", lambda: workloads.WORKLOADS["tgv_n3_4x4x4_curved"], "fp64"),
+    ("tgv_n3 curved mixed", lambda: workloads.WORKLOADS["tgv_n3_4x4x4_curved"], "mixed"),
 ]
 
 
