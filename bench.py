@@ -64,11 +64,11 @@ COUNTED_TRAFFIC = {"sources_sha256_prefix": "dfaa36e09b1578e5", "bytes_per_launc
 TRAFFIC_SOURCES = ("fwd_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 # The same for k_rhs_curv<7,double,true,true,false> on the curved workload
 # (profiles/k_rhs_curv_k_face_flux_curv_tgv_n7_32x32x32_curved.md): reads
-# 128 x 46,462,404.1 RDREQ_128B + 64 x 2,012.4 RDREQ_64B, writes 1,310,720 KiB;
+# 128 x 47,179,152.3 RDREQ_128B + 64 x 2,081.0 RDREQ_64B, writes 1,310,720 KiB;
 # and for its mixed-precision instance k_rhs_curv<7,float,true,true,false>:
-# reads 128 x 42,520,703.7 RDREQ_128B + 64 x 8,480.2 RDREQ_64B, same writes.
-COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "4c5d4294668cc649", "bytes_per_launch": 7289493794.0}
-COUNTED_TRAFFIC_CURVED_MIXED = {"sources_sha256_prefix": "4c5d4294668cc649", "bytes_per_launch": 6785370082.0}
+# reads 128 x 34,049,318.5 RDREQ_128B + 64 x 6,760.8 RDREQ_64B, same writes.
+COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "fe7ab567a73f99a8", "bytes_per_launch": 7381241954.0}
+COUNTED_TRAFFIC_CURVED_MIXED = {"sources_sha256_prefix": "fe7ab567a73f99a8", "bytes_per_launch": 5700922735.0}
 TRAFFIC_SOURCES_CURVED = ("curv_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 
 

@@ -103,8 +103,11 @@ typedef struct {
                          metric vector); faces may be NULL.  DG_FP64 with either
                          flux pair (the Roe flux along the face's unit normal,
                          scaled by its length), DG_MIXED with the
-                         Kennedy-Gruber pair; no wall model, adjoint,
-                         lifting or kinetic-energy calls (DG_EUNSUPPORTED).  A non-positive Jacobian at any node
+                         Kennedy-Gruber pair only; DG_MIXED with the
+                         entropy-conserving pair, the wall model and the
+                         adjoint, lifting or kinetic-energy calls give
+                         DG_EUNSUPPORTED.  The workspace holds the metric
+                         terms, 10 FP64 + 10 FP32 values per DOF.  A non-positive Jacobian at any node
                          makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;
 

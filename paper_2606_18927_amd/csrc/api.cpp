@@ -85,7 +85,7 @@ Layout layout(const dg_ctx* c) {
   L.G = take(state);
   L.ffv = c->phys.viscous ? take(fbytes) : off;
   L.tauw = c->wall_model ? take(static_cast<size_t>(c->n_wall_faces) * 3 * NP * NP * sizeof(double)) : off;
-  L.geo = c->curvilinear ? take(10 * dof * sizeof(double)) : off;
+  L.geo = c->curvilinear ? take(10 * dof * (sizeof(double) + sizeof(float))) : off;  // FP64 + FP32 copy
   L.fwd_end = off;
   L.stages = take(5 * state);
   L.lamG = take(state);

@@ -8,7 +8,8 @@
 // with the collocation derivative D for every xi-derivative, so the discrete
 // metric identities hold and both elements of a face see the same normal;
 // J = det(dX/dxi).  k_metrics computes them once per mesh into
-//   geo[c][e][node], c = 3 i + n: J a^i_n; c = 9: 1 / J.
+//   geo[c][e][node], c = 3 i + n: J a^i_n; c = 9: 1 / J; then the same ten
+//   fields in FP32 (read by the mixed-precision sweeps).
 // Operator per stage (one workgroup per element, one lane per node; face
 // lanes = one lane per face node):
 //   k_face_flux_curv  BR1 gradients at the face nodes (chain rule with the
@@ -177,6 +178,11 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __rest
 #pragma unroll
     for (int c = 0; c < 9; ++c) geo[c * stride + o] = Ja[c];
     geo[9 * stride + o] = 1.0 / J;
+    // FP32 copy for the mixed-precision sweeps, after the ten FP64 fields
+    float* const g32 = reinterpret_cast<float*>(geo + 10 * stride);
+#pragma unroll
+    for (int c = 0; c < 9; ++c) g32[c * stride + o] = static_cast<float>(Ja[c]);
+    g32[9 * stride + o] = static_cast<float>(1.0 / J);
   }
 }
 
@@ -236,6 +242,16 @@ __device__ inline void load_geo(const double* geo, long long stride, long long i
 #pragma unroll
   for (int c = 0; c < 9; ++c) Ja[c] = geo[c * stride + idx];
   invJ = geo[9 * stride + idx];
+}
+
+// Metric field c at node idx in the sweep precision: the FP64 field, or its
+// FP32 copy stored after the ten FP64 fields.
+template <typename R>
+__device__ inline R geo_at(const double* geo, long long stride, int c, long long idx) {
+  if constexpr (sizeof(R) == sizeof(float))
+    return reinterpret_cast<const float*>(geo + 10 * stride)[c * stride + idx];
+  else
+    return geo[c * stride + idx];
 }
 
 // ---------------------------------------------------------- face viscous flux
@@ -437,14 +453,12 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   R tau[6] = {0, 0, 0, 0, 0, 0}, qT[3] = {0, 0, 0};
   if (VISC) {
     if (active) {
-      double Ja[9], invJ;
-      load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
-      R Jr[9];
+      R Jr[10];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) Jr[c] = static_cast<R>(Ja[c]);
+      for (int c = 0; c < 10; ++c) Jr[c] = geo_at<R>(mesh.geo, stride, c, e * NN + tid);
       const R* const q[4] = {sp[1], sp[2], sp[3], sT};
       R g[12];
-      curv_gradients<N, R>(q, sD, corr, i, j, k, Jr, static_cast<R>(invJ), g);
+      curv_gradients<N, R>(q, sD, corr, i, j, k, Jr, Jr[9], g);
       const double r = viscosity_ratio(ph, static_cast<double>(sT[tid]) + T_ref);
       stress64<R>(g, static_cast<R>(ph.mu * r), static_cast<R>(ph.kappa * r), tau, qT);
     }
@@ -460,9 +474,9 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     R M0 = 0, M1 = 0, M2 = 0, A[6] = {1, 0, 0, 0, 1, 1};
     if (active) {
       const long long gi = e * NN + tid;
-      M0 = static_cast<R>(mesh.geo[(3 * d) * stride + gi]);
-      M1 = static_cast<R>(mesh.geo[(3 * d + 1) * stride + gi]);
-      M2 = static_cast<R>(mesh.geo[(3 * d + 2) * stride + gi]);
+      M0 = geo_at<R>(mesh.geo, stride, 3 * d, gi);
+      M1 = geo_at<R>(mesh.geo, stride, 3 * d + 1, gi);
+      M2 = geo_at<R>(mesh.geo, stride, 3 * d + 2, gi);
 #pragma unroll
       for (int c = 0; c < 6; ++c) A[c] = sp[c][tid];
       sM[0][tid] = M0;
