@@ -7,8 +7,13 @@ face viscous-flux kernel and a fused lifting + right-hand-side + RK-update kerne
 
 Prints one JSON line.  `value` is ns per DOF per RK stage (FP64), i.e. the
 paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
-  roofline      the fused RHS/RK kernel's algorithmic HBM bytes per launch over
-                its mean launch time (HIP events on the launch stream) vs 8 TB/s;
+  roofline      the fused RHS/RK kernel's algorithmic HBM bytes per launch (256
+                B per DOF: read U, the 12 lifted gradient components and G,
+                write G and U) over its mean launch time (HIP events on the
+                launch stream) vs 8 TB/s; the step at 392 B per DOF; this
+                design's own smaller traffic beside it;
+  fp64_compute  algorithmic FP64 flops per DOF and stage over the step time vs
+                78.6 TFLOP/s (and the rocprofv3-counted flops while valid);
   cpu_baseline  the CPU oracle timed on a bounded sample of the same workload;
   mixed         the same step in mixed precision (when requested / available);
   ec_roe        the same step with the entropy-conserving volume flux and the
@@ -20,7 +25,11 @@ paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
                 Sutherland's law (FP64) beside the same channel with
                 isothermal walls and constant viscosity, and the wall-stress
                 kernel alone (algorithmic bytes over its event-timed launch);
-  adjoint       adjoint/forward time ratio (when available).
+  freestream_context  the paper's throughput workload (uniform free stream,
+                N = 7, same mesh), FP64;
+  adjoint       the N = 5, 48x32x48 channel, 500 steps, checkpoint every 25:
+                mixed forward, FP64 adjoint; adjoint/forward time ratio,
+                memory, gradient error against the all-FP64 gradient.
 """
 
 from __future__ import annotations
@@ -49,11 +58,28 @@ def alg_bytes(precision: str, N: int = 7):
     return {"face": 40 + ff, "rk": 40 + ff + 40 + 40 + 40, "rk_first": 40 + ff + 40 + 40}
 
 
-# Bytes per DOF and stage of the stored-gradient design (a lifting kernel that
-# writes the 12 gradient components, then a right-hand side that reads them):
-# the figure the 60 % roofline target is stated against.  Reported beside the
-# fraction of this design's own algorithmic bytes.
+# The method's algorithmic HBM bytes per DOF and RK stage, counted for a
+# lifting kernel that writes the 12 lifted gradient components and a
+# right-hand-side stage kernel that reads them (8 B per FP64 value):
+#   right-hand side + RK stage: read U (40) + gradients (96) + G (40),
+#                               write G (40) + U (40)          = 256 B
+#   whole stage: + lifting (read U 40, write gradients 96)     = 392 B
+# The roofline entry prices the dominant kernel (the fused right-hand side +
+# RK stage) at the 256 B it stands for, the step at 392 B; this design's own
+# smaller traffic (gradients recomputed, never stored) is reported beside it.
+RHS_STAGE_BYTES_PER_DOF = 256.0
 STORED_GRADIENT_BYTES_PER_DOF = 392.0
+
+# Algorithmic FP64 flops per DOF and RK stage at N = 7 (Cartesian elements,
+# pairs evaluated once per symmetric pair, a division counted as one):
+# Kennedy-Gruber pairs 417, lifting sweeps 192, viscous-flux sweeps 192,
+# viscous flux 44, surface fluxes (0.375 face nodes per DOF) 40, primitives
+# 20, RK update 20, scaling 15.
+ALG_FLOPS_PER_DOF_STAGE = 940.0
+# FP64 flops per DOF and stage counted with rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,
+# FMA,TRANS}_F64 x 64 lanes, FMA twice) on k_rhs + k_face_flux of this
+# workload; valid only for the kernel sources they were counted on.
+COUNTED_FLOPS = {"sources_sha256_prefix": "dfaa36e09b1578e5", "per_dof_stage": 1323.0 + 219.0}
 
 # HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
 # counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
@@ -73,6 +99,8 @@ TRAFFIC_SOURCES_CURVED = ("curv_kernels.hip", "dg_device.hpp", "dg_internal.hpp"
 
 
 def counted_traffic(counted=COUNTED_TRAFFIC, sources=TRAFFIC_SOURCES):
+    """A counted figure (bytes or flops) if the kernel sources still hash to
+    the value it was counted on, else None."""
     import hashlib
     h = hashlib.sha256()
     for f in sources:
@@ -80,7 +108,7 @@ def counted_traffic(counted=COUNTED_TRAFFIC, sources=TRAFFIC_SOURCES):
             h.update(fh.read())
     if h.hexdigest()[:16] != counted["sources_sha256_prefix"]:
         return None
-    return counted["bytes_per_launch"]
+    return counted["bytes_per_launch"] if "bytes_per_launch" in counted else counted["per_dof_stage"]
 
 
 def _parse():
@@ -96,7 +124,8 @@ def _parse():
     ap.add_argument("--no-curved", action="store_true", help="skip the curved-element leg")
     ap.add_argument("--no-physics", action="store_true",
                     help="skip the Sutherland and wall-model legs")
-    ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--adjoint-steps", type=int, default=500,
+                    help="steps of the adjoint leg (the channel case as configured: 500, K = 25)")
     return ap.parse_args()
 
 
@@ -371,10 +400,14 @@ def run_small_graph(steps: int, warmup: int):
 
 
 def run_adjoint(steps: int, K: int):
-    """Adjoint/forward time ratio on the N=5, 48x32x48 stretched channel:
-    mixed-precision forward RK rollout, then the checkpointed FP64 adjoint of
-    the final kinetic energy (forward with checkpoints + segment recompute +
-    reverse steps) against the plain forward of the same steps."""
+    """Adjoint/forward time ratio on the N=5, 48x32x48 stretched channel as
+    configured: a mixed-precision forward RK rollout of `steps` steps, then the
+    checkpointed FP64 adjoint of the final kinetic energy (forward with a
+    checkpoint every K steps, the last segment's stages recorded, the other
+    segments recomputed once, reverse steps) against the plain forward of the
+    same steps.  The gradient is compared per conserved variable with the
+    all-FP64 (forward and adjoint) gradient of the same rollout."""
+    import numpy as np
     import torch
 
     from paper_2606_18927_amd import dgsem, workloads
@@ -385,6 +418,7 @@ def run_adjoint(steps: int, K: int):
     U, dt = workloads.make_state(wl, xi)
     S = dgsem.solver_for(wl, with_adjoint=True)
     Ud = torch.as_tensor(U.reshape(-1)).cuda()
+    del U
     S.set_state(Ud)
     S.rk_step(dt, 2)
     S.sync()
@@ -397,6 +431,7 @@ def run_adjoint(steps: int, K: int):
     S.sync()
     torch.cuda.synchronize()
     t_fwd = a.elapsed_time(b)
+    torch.cuda.empty_cache()
     torch.cuda.reset_peak_memory_stats()
     base_mem = torch.cuda.memory_allocated()
     a, b = ev()
@@ -406,23 +441,21 @@ def run_adjoint(steps: int, K: int):
     torch.cuda.synchronize()
     t_adj = a.elapsed_time(b)
     peak_extra = torch.cuda.max_memory_allocated() - base_mem
-    # the same adjoint with every segment's stages recorded in the forward pass
-    # (no recompute), when they fit in the free HBM with 16 GB to spare
-    seg_bytes = K * 25 * S.n_dof * 8
-    nseg = -(-steps // K)
-    all_rec = None
+    print(f"[bench] adjoint {steps} steps, K = {K}: forward {t_fwd:.0f} ms, forward + adjoint {t_adj:.0f} ms",
+          file=sys.stderr, flush=True)
+    dof = S.n_dof
+    ws_gb = S.workspace_bytes / 1e9
+    del S
     torch.cuda.empty_cache()
-    if torch.cuda.mem_get_info()[0] > nseg * seg_bytes + (16 << 30):
-        torch.cuda.reset_peak_memory_stats()
-        a, b = ev()
-        a.record(S.stream)
-        J2, g2 = kinetic_energy_gradient(S, Ud, dt, steps, checkpoint_every=K, stage_memory_bytes=nseg * seg_bytes)
-        b.record(S.stream)
-        torch.cuda.synchronize()
-        all_rec = {"adjoint_total_ms": a.elapsed_time(b), "adjoint_forward_ratio": a.elapsed_time(b) / t_fwd,
-                   "extra_peak_gb": (torch.cuda.max_memory_allocated() - base_mem) / 1e9,
-                   "same_gradient": bool(torch.equal(g, g2))}
-        del g2
+    # the all-FP64 reference gradient of the same rollout
+    S64 = dgsem.solver_for(wl, with_adjoint=True, precision="fp64")
+    J64, g64 = kinetic_energy_gradient(S64, Ud, dt, steps, checkpoint_every=K)
+    torch.cuda.synchronize()
+    gv, rv = g.view(5, -1), g64.view(5, -1)
+    grad_err = ((gv - rv).norm(dim=1) / rv.norm(dim=1)).cpu().numpy()
+    grad_max = ((gv - rv).abs().amax(dim=1) / rv.abs().amax(dim=1)).cpu().numpy()
+    del S64, g64, g
+    torch.cuda.empty_cache()
     # kernel level: one right-hand side vs one vector-Jacobian product (FP64),
     # for both flux pairs
     lam = torch.randn_like(Ud)
@@ -450,20 +483,35 @@ def run_adjoint(steps: int, K: int):
 
     t_rhs, t_vjp = rhs_vs_vjp("kg_llf")
     t_rhs_ec, t_vjp_ec = rhs_vs_vjp("ec_roe")
-    dof = S.n_dof
+    state_gb = 5 * dof * 8 / 1e9
     res = {"workload": wl.name, "dof": dof, "steps": steps, "checkpoint_every": K,
            "forward_precision": "mixed", "adjoint_precision": "fp64",
            "forward_ms": t_fwd, "forward_ns_per_dof_stage": t_fwd * 1e6 / (dof * steps * 5),
            "adjoint_total_ms": t_adj, "adjoint_forward_ratio": t_adj / t_fwd,
+           "memory_gb": {"workspace": ws_gb, "checkpoints": (-(-steps // K) - 1) * state_gb,
+                         "recorded_stages_one_segment": K * 25 * dof * 8 / 1e9,
+                         "peak_beyond_state_and_workspace": peak_extra / 1e9},
+           "gradient_vs_fp64": {"rel_l2_per_variable": [float(x) for x in grad_err],
+                                "rel_max_per_variable": [float(x) for x in grad_max],
+                                "J_rel_diff": abs(J.item() - J64.item()) / abs(J64.item())},
            "eval_rhs_fp64_ms": t_rhs, "eval_rhs_vjp_fp64_ms": t_vjp, "vjp_rhs_ratio": t_vjp / t_rhs,
            "ec_roe": {"eval_rhs_fp64_ms": t_rhs_ec, "eval_rhs_vjp_fp64_ms": t_vjp_ec,
                       "vjp_rhs_ratio": t_vjp_ec / t_rhs_ec},
-           "workspace_gb": S.workspace_bytes / 1e9, "adjoint_extra_peak_gb": peak_extra / 1e9,
-           "all_segments_recorded": all_rec,
            "J": J.item()}
-    del S
     torch.cuda.empty_cache()
     return res
+
+
+def run_freestream(steps: int, warmup: int):
+    """The paper's throughput workload (a uniform free stream in the periodic
+    box, N = 7; its PID does not depend on the solution) on the 32^3 mesh,
+    FP64: a context row beside the Taylor-Green value."""
+    from paper_2606_18927_amd import dgsem, workloads
+    wl = workloads.WORKLOADS["freestream_n7_32x32x32"]
+    xi, _ = dgsem.lgl(wl.N)
+    U, dt = workloads.make_state(wl, xi)
+    r, _ = run_precision(wl, U, dt, "fp64", steps, warmup)
+    return _leg(wl.name, r)
 
 
 def main():
@@ -557,15 +605,17 @@ def main():
         small = run_small_graph(100, 5)
         print(f"[bench] {small['workload']}: {small['eager_us_per_step']:.1f} us/step launched, "
               f"{small['graph_us_per_step']:.1f} us/step from a HIP graph", file=sys.stderr, flush=True)
+    freestream = None
+    if wl.name == "tgv_n7_32x32x32":
+        freestream = run_freestream(args.steps, args.warmup)
+        print(f"[bench] free stream {freestream['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
+              flush=True)
     adjoint = None
     if not args.no_adjoint:
         adjoint = run_adjoint(args.adjoint_steps, 25)
-        ar = adjoint["all_segments_recorded"]
-        if ar:
-            print(f"[bench] adjoint/forward with every segment recorded in the forward pass "
-                  f"{ar['adjoint_forward_ratio']:.2f} ({ar['extra_peak_gb']:.0f} GB)", file=sys.stderr, flush=True)
-        print(f"[bench] adjoint/forward {adjoint['adjoint_forward_ratio']:.2f}; vjp/rhs kg_llf "
-              f"{adjoint['vjp_rhs_ratio']:.2f}, ec_roe {adjoint['ec_roe']['vjp_rhs_ratio']:.2f}",
+        print(f"[bench] adjoint/forward {adjoint['adjoint_forward_ratio']:.2f} "
+              f"(gradient vs FP64 rel L2 max {max(adjoint['gradient_vs_fp64']['rel_l2_per_variable']):.1e}); "
+              f"vjp/rhs kg_llf {adjoint['vjp_rhs_ratio']:.2f}, ec_roe {adjoint['ec_roe']['vjp_rhs_ratio']:.2f}",
               file=sys.stderr, flush=True)
     triad = triad_gbs()
     print(f"[bench] triad {triad:.0f} GB/s", file=sys.stderr, flush=True)
@@ -573,6 +623,13 @@ def main():
 
     value = fp64["ns_per_dof_stage"]
     traffic = counted_traffic() if wl.name == "tgv_n7_32x32x32" else None
+    dof = fp64["dof"]
+    rk_s = fp64["rk_kernel_ms"] / 1e3
+    alg_rk_bytes = RHS_STAGE_BYTES_PER_DOF * dof          # per launch
+    achieved = alg_rk_bytes / rk_s / 1e9
+    counted_flops = counted_traffic(COUNTED_FLOPS) if wl.name == "tgv_n7_32x32x32" else None
+    step_s_per_stage = value * 1e-9 * dof                 # seconds per RK stage
+    alg_tflops = ALG_FLOPS_PER_DOF_STAGE * dof / step_s_per_stage / 1e12
     out = {
         "metric": METRIC,
         "value": value,
@@ -592,25 +649,38 @@ def main():
         "repeats_ns_per_dof_stage": fp64["repeats_ns_per_dof_stage"],
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_rhs (fused RHS + RK stage)",
-            "achieved": fp64["rk_kernel_gbs"],
+            "kernel": "k_rhs (fused right-hand side + RK stage)",
+            "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": fp64["rk_kernel_gbs"] / HBM_PEAK_GBS,
+            "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "traffic_unit": "bytes per launch (rocprofv3 TCC_EA0_RDREQ_{32,64,128}B + WRITE_SIZE)",
-            "traffic_over_algorithmic": None if traffic is None else traffic / fp64["rk_bytes_per_launch"],
-            "traffic_gbs": None if traffic is None else traffic / (fp64["rk_kernel_ms"] / 1e3) / 1e9,
+            "alg_bytes_per_dof": RHS_STAGE_BYTES_PER_DOF,
+            "alg_bytes_per_launch": alg_rk_bytes,
             "kernel_ms": fp64["rk_kernel_ms"],
-            "bytes_per_launch": fp64["rk_bytes_per_launch"],
-            "face_kernel_gbs": fp64["face_kernel_gbs"],
+            "traffic_unit": "bytes per launch (rocprofv3 TCC_EA0_RDREQ_{32,64,128}B + WRITE_SIZE)",
+            "traffic_gbs": None if traffic is None else traffic / rk_s / 1e9,
+            "own_bytes_per_launch": fp64["rk_bytes_per_launch"],
+            "own_bytes_gbs": fp64["rk_kernel_gbs"],
+            "frac_own_bytes": fp64["rk_kernel_gbs"] / HBM_PEAK_GBS,
+            "traffic_over_own_bytes": None if traffic is None else traffic / fp64["rk_bytes_per_launch"],
             "face_kernel_ms": fp64["face_kernel_ms"],
-            "step_alg_bytes_per_dof": fp64["step_alg_bytes_per_dof"],
-            "step_alg_gbs": fp64["step_alg_gbs"],
-            "step_frac": fp64["step_alg_gbs"] / HBM_PEAK_GBS,
+            "face_kernel_gbs": fp64["face_kernel_gbs"],
+            "step_alg_bytes_per_dof": STORED_GRADIENT_BYTES_PER_DOF,
+            "step_frac": STORED_GRADIENT_BYTES_PER_DOF / value / HBM_PEAK_GBS,
+            "step_own_bytes_per_dof": fp64["step_alg_bytes_per_dof"],
+            "step_frac_own_bytes": fp64["step_alg_gbs"] / HBM_PEAK_GBS,
             "triad_gbs": triad,
-            "step_frac_of_triad": fp64["step_alg_gbs"] / triad,
-            "step_frac_at_stored_gradient_bytes": STORED_GRADIENT_BYTES_PER_DOF / value / HBM_PEAK_GBS,
+            "step_frac_of_triad": STORED_GRADIENT_BYTES_PER_DOF / value / triad,
+        },
+        "fp64_compute": {
+            "alg_flop_per_dof_stage": ALG_FLOPS_PER_DOF_STAGE,
+            "achieved_tflops": alg_tflops,
+            "peak_tflops": FP64_PEAK_TFLOPS,
+            "frac": alg_tflops / FP64_PEAK_TFLOPS,
+            "counted_flop_per_dof_stage": counted_flops,
+            "counted_frac": None if counted_flops is None else
+            counted_flops * dof / step_s_per_stage / 1e12 / FP64_PEAK_TFLOPS,
         },
         "cpu_baseline": cpu,
         "mixed": mixed,
@@ -620,6 +690,7 @@ def main():
         "wall_model": wall,
         "adjoint": adjoint,
         "small_case_graph": small,
+        "freestream_context": freestream,
         "context_mi300a_pid_ns": {"range": [2.457, 4.260], "note": "paper Table 1, 32 APUs, N=7 free stream"},
     }
     print(json.dumps(out))

@@ -138,6 +138,11 @@ dg_status dg_lgl(int N, double* xi, double* w);
 
 /* Validate the mesh and physics, build the host tables and create a context
  * on `hip_stream` (a hipStream_t, NULL = default stream).  No device work.
+ * The mesh is the paper's element decomposition (Sec. 2.1-2.2: hexahedral
+ * elements, each with (N+1)^3 LGL collocation nodes); the physics are the
+ * ideal gas with viscous fluxes of Sec. 4 and the flux pairs above.  The
+ * context copies everything it needs from `mesh` and `phys`; the caller keeps
+ * ownership of both.  On error *out is left unchanged.
  * Errors: DG_EINVAL (null pointers, non-monotone faces, bad bc, gamma <= 1,
  * R <= 0, mu < 0, Pr <= 0, empty mesh, unknown precision, flux or viscosity
  * law, Sutherland's law with T_ref <= 0 or S < 0),
@@ -157,10 +162,16 @@ dg_status dg_n_dof(const dg_ctx* ctx, long long* n_dof);
  * and upload the tables.  May be called again to rebind.                      */
 dg_status dg_bind_workspace(dg_ctx* ctx, void* dev_ptr, size_t bytes, int with_adjoint);
 
-/* Copy a state (layout above) into the context and clear the RK register. */
+/* Copy a state (layout above) into the context and clear the RK register:
+ * the initial value U(t0) of the semi-discrete system dU/dt = L(U) (paper
+ * Sec. 2.2) that dg_rk_step advances.  U_dev (device, 5 n_dof doubles, caller
+ * owned) is read on the context's stream.  Errors: DG_EINVAL (null pointer),
+ * DG_ESTATE (no workspace bound).                                            */
 dg_status dg_set_state(dg_ctx* ctx, const double* U_dev);
 
-/* Copy the context's current state out. */
+/* Copy the context's current state (the RK solution of paper Sec. 4 after
+ * the steps taken so far) to U_dev (device, 5 n_dof doubles, caller owned),
+ * asynchronously on the context's stream.  Errors: DG_EINVAL, DG_ESTATE.   */
 dg_status dg_get_state(const dg_ctx* ctx, double* U_dev);
 
 /* Ut = L(U) (paper Sec. 2.2 semi-discrete operator).  U and Ut must not overlap.
@@ -189,7 +200,12 @@ dg_status dg_rk_step(dg_ctx* ctx, double t, double dt, int nsteps);
 dg_status dg_rk_graph_build(dg_ctx* ctx, double dt, int nsteps);
 dg_status dg_rk_graph_launch(dg_ctx* ctx, int repeats);
 
-/* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs.  Needs a
+/* Ubar = (dL/dU (U))^T lam: vector-Jacobian product of dg_eval_rhs, i.e. the
+ * transpose of the linearised split-form DG operator of paper Sec. 2.2 (BR1
+ * lifting, two-point volume flux differencing, surface fluxes, surface
+ * lifting and Jacobian scaling, each differentiated by hand).  U, lam and
+ * Ubar are device arrays of 5 n_dof doubles in the state layout, caller
+ * owned; Ubar must not overlap U or lam.  Needs a
  * workspace bound with_adjoint.  FP64 arithmetic.  The VJP calls cover
  * axis-aligned elements with isothermal or periodic ends (either flux pair,
  * either viscosity law); curved elements and the wall model get
@@ -199,7 +215,13 @@ dg_status dg_eval_rhs_vjp(dg_ctx* ctx, const double* U_dev, const double* lam_de
                           double* Ubar_dev, double t);
 
 /* One RK step backwards: given U_n and lamU_np1 = dJ/dU_{n+1}, write
- * lamU_n = dJ/dU_n (recomputes the five stage states internally).           */
+ * lamU_n = dJ/dU_n, the transpose of one step of the five-stage low-storage
+ * RK scheme (paper Sec. 4) linearised at U_n: per stage in reverse order
+ * lamG += B_s lamU, lamU += dt (dL/dU(U_{n,s}))^T lamG, lamG <- A_s lamG
+ * (recomputes the five stage states internally in the context's precision;
+ * the VJPs are FP64).  Device arrays of 5 n_dof doubles, caller owned;
+ * lamU_n may alias lamU_np1.  Errors: DG_EINVAL, DG_ESTATE (no adjoint
+ * workspace), DG_EUNSUPPORTED (curved elements, wall model).                */
 dg_status dg_rk_step_vjp(dg_ctx* ctx, const double* U_n_dev, double t, double dt,
                          const double* lamU_np1_dev, double* lamU_n_dev);
 
@@ -254,7 +276,10 @@ dg_status dg_kinetic_energy_grad(dg_ctx* ctx, const double* U_dev, double* lam_d
 
 /* STREAM triad a[i] = b[i] + s c[i] over n doubles on hip_stream (device
  * pointers, caller owned): the measured HBM ceiling the operator's achieved
- * bandwidth is compared with.  Asynchronous; no context needed.             */
+ * bandwidth is compared with (24 bytes per element).  With 16-byte aligned
+ * pointers every lane moves 16-byte pairs; otherwise 8-byte elements.
+ * Asynchronous; no context needed.  Errors: DG_EINVAL (null pointer, n < 0),
+ * DG_EHIP (launch failed).                                                   */
 dg_status dg_stream_triad(const double* b_dev, const double* c_dev, double s, double* a_dev,
                           long long n, void* hip_stream);
 

@@ -111,7 +111,11 @@ dg::DevMesh dev_mesh(const dg_ctx* c) {
   return m;
 }
 
-dg::DevPhys dev_phys(const dg_ctx* c) {
+dg::DevPhys dev_phys(const dg_ctx* c) { return dg::device_physics(c); }
+
+}  // namespace
+
+dg::DevPhys dg::device_physics(const dg_ctx* c) {
   dg::DevPhys p{};
   p.gamma = c->phys.gamma;
   p.gm1 = c->phys.gamma - 1.0;
@@ -129,6 +133,8 @@ dg::DevPhys dev_phys(const dg_ctx* c) {
   p.suth_c = p.suth ? (c->phys.T_ref + c->phys.S) / (c->phys.T_ref * std::sqrt(c->phys.T_ref)) : 1.0;
   return p;
 }
+
+namespace {
 
 dg::DevBasis dev_basis(const dg_ctx* c) {
   dg::DevBasis b{};

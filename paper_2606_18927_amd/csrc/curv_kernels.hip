@@ -449,11 +449,16 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     __syncthreads();
   }
 
-  // P2: gradients, stress and heat flux
+  // P2: gradients, stress and heat flux.  With the Kennedy-Gruber pair the
+  // metric terms read here stay in registers for the sweeps (and, in FP64,
+  // 1/J for the output): read again after P2 they miss in L2.  The
+  // entropy-conserving instances and degree 3 have no registers to spare and
+  // read them again.
+  constexpr bool KEEP = VISC && !EC && N >= 5;
   R tau[6] = {0, 0, 0, 0, 0, 0}, qT[3] = {0, 0, 0};
+  R Jr[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (VISC) {
     if (active) {
-      R Jr[10];
 #pragma unroll
       for (int c = 0; c < 10; ++c) Jr[c] = geo_at<R>(mesh.geo, stride, c, e * NN + tid);
       const R* const q[4] = {sp[1], sp[2], sp[3], sT};
@@ -474,9 +479,15 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     R M0 = 0, M1 = 0, M2 = 0, A[6] = {1, 0, 0, 0, 1, 1};
     if (active) {
       const long long gi = e * NN + tid;
-      M0 = geo_at<R>(mesh.geo, stride, 3 * d, gi);
-      M1 = geo_at<R>(mesh.geo, stride, 3 * d + 1, gi);
-      M2 = geo_at<R>(mesh.geo, stride, 3 * d + 2, gi);
+      if (KEEP) {
+        M0 = d == 0 ? Jr[0] : (d == 1 ? Jr[3] : Jr[6]);
+        M1 = d == 0 ? Jr[1] : (d == 1 ? Jr[4] : Jr[7]);
+        M2 = d == 0 ? Jr[2] : (d == 1 ? Jr[5] : Jr[8]);
+      } else {
+        M0 = geo_at<R>(mesh.geo, stride, 3 * d, gi);
+        M1 = geo_at<R>(mesh.geo, stride, 3 * d + 1, gi);
+        M2 = geo_at<R>(mesh.geo, stride, 3 * d + 2, gi);
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c) A[c] = sp[c][tid];
       sM[0][tid] = M0;
@@ -695,7 +706,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   // P5: surface terms, 1/J, output
   if (active) {
     double gA[5] = {0, 0, 0, 0, 0};
-    const double invJ = mesh.geo[9 * stride + e * NN + tid];
+    const double invJ = KEEP && !MIXED ? static_cast<double>(Jr[9]) : mesh.geo[9 * stride + e * NN + tid];
     if (RK && st.read_G) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];

@@ -25,13 +25,21 @@ struct Cfg<7> {
   static constexpr int EPB = 1, BS = 512, FACE_WAVES = 8;
 };
 
-template <int N, int PAD = 1>
+// LDS block of one element and field: x-rows of RS entries (NP + PAD); with
+// SWZ (NP a power of two, no padding) node i of row j sits at slot i ^ j of
+// its row, so the NP rows that the lanes of a wave read at one x-position m
+// (an x-line sweep) start in different banks, while a y- or z-line sweep
+// still reads whole rows (a permutation of them).
+template <int N, int PAD = 1, bool SWZ = false>
 struct Geo {
   static constexpr int NP = N + 1, NF = NP * NP, NN = NF * NP;
   static constexpr int RS = NP + PAD;      // x-row stride of an LDS block
   static constexpr int EB = RS * NP * NP;  // LDS entries per element and field
   static constexpr int DS = NP + 1;        // padded row stride of D in LDS
-  __device__ static constexpr int lds(int i, int j, int k) { return i + RS * (j + NP * k); }
+  static_assert(!SWZ || (PAD == 0 && (NP & (NP - 1)) == 0), "the swizzle permutes unpadded rows of 2^n");
+  __device__ static constexpr int lds(int i, int j, int k) {
+    return (SWZ ? (i ^ (j & (NP - 1))) : i) + RS * (j + NP * k);
+  }
 };
 
 template <int N>

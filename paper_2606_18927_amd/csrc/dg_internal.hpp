@@ -9,6 +9,8 @@
 
 #include "../../include/dgsem.h"
 
+struct dg_ctx;
+
 namespace dg {
 
 constexpr int kMaxN = 7;
@@ -91,6 +93,9 @@ hipError_t launch_rhs_curv(int N, int precision, const DevMesh& m, const DevPhys
 hipError_t launch_rk_stage_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
                                 const double* U, const void* ffv, double* G, double* U_out,
                                 const Stage& st, int* status, hipStream_t s);
+
+// Gas constants and switches of a context as the kernels take them (api.cpp).
+DevPhys device_physics(const dg_ctx* c);
 
 // Wall-stress model: number of wall faces of the mesh, and the kernel (one
 // lane per wall-face node).

@@ -358,61 +358,15 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<
 // k_rhs
 // --------------------------------------------------------------------------
 
-// LDS layout of k_rhs: unpadded x-rows.  Its 128-bit accesses are
-// conflict-free either way and its 64-bit z-line reads only without the
-// padding (measured 3.6 % faster); k_face_flux keeps padded rows, which its
-// ring lanes need.
+// LDS layout of k_rhs: unpadded x-rows, swizzled where N + 1 is a power of
+// two.  In an x-line sweep the eight lanes of a row read one address and the
+// wave reads NP rows at the same x-position: 128-bit reads of unswizzled rows
+// then meet in the same banks (measured 9.0 instead of 4.9 CU cycles per wave
+// read; padded rows fix that but slow the z-line reads to 9.2); the swizzle
+// reads 5.0, 4.8 and 4.9 cycles in x, y and z.  k_face_flux keeps padded rows,
+// which its ring lanes need.
 template <int N>
-using GeoR = Geo<N, 0>;
-
-// Line sums of direction d at node (i, j, k): ac = sum_m D_im f#_KG(own, m),
-// av = sum_m D_im f_v,d(m), du = sum_m D_im u_d,m / 2 (mixed-precision add-back).
-// Own and line values are halves: a, b = ((rho, u), (v, w), (p, e)) / 2, so that
-// {{x}} = a.x + b.x exactly as (x_a + x_b) / 2.  The Kennedy-Gruber flux
-//   f# = ({{rho}}{{u_d}}, {{rho}}{{u_d}}{{u}} + {{p}} delta_1d, ...,
-//         {{u_d}} ({{rho}}{{e}} + {{p}}))
-// enters the sums premultiplied by D_im: with s = D_im {{u_d}} and
-// m = s {{rho}}, the five components take m, m {{u}}, m {{v}}, m {{w}}
-// (+ D_im {{p}} in component 1 + d) and s ({{rho}}{{e}} + {{p}}).
-template <int N, typename R, int d, bool VISC, bool MIXED, typename V2>
-__device__ inline void volume_sweep(const V2 (&own)[3], int i, int j, int k, const R* sD,
-                                    const V2 (*sp)[GeoR<N>::EB], const V2 (*sfv)[GeoR<N>::EB],
-                                    R ac[5], R av[4], R& du) {
-  using Gm = GeoR<N>;
-  constexpr int NP = Gm::NP;
-  const int idx = d == 0 ? i : (d == 1 ? j : k);
-#pragma unroll
-  for (int v = 0; v < 5; ++v) ac[v] = R(0);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) av[c] = R(0);
-  du = R(0);
-#pragma unroll
-  for (int m = 0; m < NP; ++m) {
-    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
-    const R Dim = sD[idx * Gm::DS + m];
-    const V2 b0 = sp[0][lm], b1 = sp[1][lm], b2 = sp[2][lm];
-    const R rho = own[0].x + b0.x;
-    const R u = own[0].y + b0.y, v = own[1].x + b1.x, w = own[1].y + b1.y;
-    const R p = own[2].x + b2.x, e = own[2].y + b2.y;
-    const R ud = d == 0 ? u : (d == 1 ? v : w);
-    const R s = Dim * ud;
-    const R mm = s * rho;
-    ac[0] += mm;
-    ac[1] += mm * u;
-    ac[2] += mm * v;
-    ac[3] += mm * w;
-    ac[1 + d] += Dim * p;
-    ac[4] += s * (rho * e + p);
-    if (MIXED) du += Dim * (d == 0 ? b0.y : (d == 1 ? b1.x : b1.y));
-    if (VISC) {
-      const V2 f01 = sfv[0][lm], f23 = sfv[1][lm];
-      av[0] += Dim * f01.x;
-      av[1] += Dim * f01.y;
-      av[2] += Dim * f23.x;
-      av[3] += Dim * f23.y;
-    }
-  }
-}
+using GeoR = Geo<N, 0, ((N + 1) & N) == 0>;
 
 // Line sums along direction d of the half values of u, v, w (packed LDS
 // fields) and of T at node (i, j, k); D is read once per line position.
@@ -469,6 +423,116 @@ __device__ inline void lifted_gradients_half(const R* sD, const V2 (*sp)[GeoR<N>
     if (k == 0) t += ssq[4][c][i + NP * j];
     if (k == N) t += ssq[5][c][i + NP * j];
     g[3 * c + 2] = sz * t;
+  }
+}
+
+// One pass over the d-line through node (i, j, k) for both the lifted
+// gradients and the convective flux differencing (Kennedy-Gruber pair, the
+// line values read from LDS once for the two):
+//   a[0..2] = sum_m D_im (u, v, w)_m / 2 and a[3] = sum_m D_im (T - T_ref)_m
+//   (VISC only), ac = sum_m D_im f#_KG(own, m), and du = sum_m D_im u_d,m / 2
+//   (the mixed-precision add-back; with VISC it is a[d]).
+// Own and line values are halves: ((rho, u), (v, w), (p - p_ref, e - e_ref)) / 2,
+// so that {{x}} = a.x + b.x exactly as (x_a + x_b) / 2.  The Kennedy-Gruber flux
+//   f# = ({{rho}}{{u_d}}, {{rho}}{{u_d}}{{u}} + {{p}} delta_1d, ...,
+//         {{u_d}} ({{rho}}{{e}} + {{p}}))
+// enters the sums premultiplied by D_im: with s = D_im {{u_d}} and
+// m = s {{rho}}, the five components take m, m {{u}}, m {{v}}, m {{w}}
+// (+ D_im {{p}} in component 1 + d) and s ({{rho}}{{e}} + {{p}}).
+template <int N, typename R, int d, bool VISC, bool MIXED, typename V2>
+__device__ inline void fused_sweep(const V2 (&own)[3], int i, int j, int k, const R* sD,
+                                   const V2 (*sp)[GeoR<N>::EB], const R* sT, R a[4], R ac[5],
+                                   R& du) {
+  using Gm = GeoR<N>;
+  constexpr int NP = Gm::NP;
+  const int idx = d == 0 ? i : (d == 1 ? j : k);
+  for (int v = 0; v < 5; ++v) ac[v] = R(0);
+  a[0] = a[1] = a[2] = a[3] = R(0);
+  du = R(0);
+  // partly unrolled (four positions at N = 7, two below): fully unrolled,
+  // the hoisted line loads and the gradient and flux sums held together
+  // spill registers
+  constexpr int UF = NP >= 8 ? 4 : 2;
+#pragma unroll UF
+  for (int m = 0; m < NP; ++m) {
+    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
+    const R Dim = sD[idx * Gm::DS + m];
+    const V2 b0 = sp[0][lm], b1 = sp[1][lm], b2 = sp[2][lm];
+    if (VISC) {
+      a[0] += Dim * b0.y;
+      a[1] += Dim * b1.x;
+      a[2] += Dim * b1.y;
+      a[3] += Dim * sT[lm];
+    } else if (MIXED) {
+      du += Dim * (d == 0 ? b0.y : (d == 1 ? b1.x : b1.y));
+    }
+    const R rho = own[0].x + b0.x;
+    const R u = own[0].y + b0.y, v = own[1].x + b1.x, w = own[1].y + b1.y;
+    const R p = own[2].x + b2.x, e = own[2].y + b2.y;
+    const R ud = d == 0 ? u : (d == 1 ? v : w);
+    const R s = Dim * ud;
+    const R mm = s * rho;
+    ac[0] += mm;
+    ac[1] += mm * u;
+    ac[2] += mm * v;
+    ac[3] += mm * w;
+    ac[1 + d] += Dim * p;
+    ac[4] += s * (rho * e + p);
+  }
+  if (VISC) du = a[d];
+}
+
+// Direction d of the fused pass: the three lifted gradient components along
+// d (line sums, BR1 lifting corrections of the d-faces, scale s_d) and the
+// convective part of the d-contribution to the right-hand side,
+// ut -= s_d 2 sum_m D_im f#_KG (plus, in mixed precision, the reference
+// state's exactly known part 2 s_d (e_ref sum D (rho u_d)# + p_ref sum D u_d)).
+template <int N, typename R, int d, bool VISC, bool MIXED, typename V2>
+__device__ inline void fused_direction(const V2 (&own)[3], int i, int j, int k, const R* sD,
+                                       const V2 (*sp)[GeoR<N>::EB], const R* sT,
+                                       const R (*ssq)[4][GeoR<N>::NF], double sd, double e_ref,
+                                       double p_ref, R g[12], double ut[5]) {
+  constexpr int NP = N + 1;
+  R a[4], ac[5], du;
+  fused_sweep<N, R, d, VISC, MIXED, V2>(own, i, j, k, sD, sp, sT, a, ac, du);
+  if (VISC) {
+    const int idx = d == 0 ? i : (d == 1 ? j : k);
+    const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
+    const R s = static_cast<R>(sd);
+    R t[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) t[c] = c < 3 ? R(2) * a[c] : a[c];  // half values: twice the line sum (exact)
+    if (idx == 0 || idx == N) {  // one branch for the two line ends
+      const int f = 2 * d + (idx == N ? 1 : 0);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] += ssq[f][c][ab];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) g[3 * c + d] = s * t[c];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) ut[v] -= sd * static_cast<double>(R(2) * ac[v]);
+  if (MIXED) ut[4] -= sd * 2.0 * (e_ref * static_cast<double>(ac[0]) + p_ref * static_cast<double>(du));
+}
+
+// av = sum_m D_im f_v,d(m) along the d-line through (i, j, k): the viscous
+// flux of direction d staged in LDS as pairs (f0, f1), (f2, f3).
+template <int N, typename R, int d, typename V2>
+__device__ inline void viscous_sweep(int i, int j, int k, const R* sD,
+                                     const V2 (*sfv)[GeoR<N>::EB], R av[4]) {
+  using Gm = GeoR<N>;
+  constexpr int NP = Gm::NP;
+  const int idx = d == 0 ? i : (d == 1 ? j : k);
+  av[0] = av[1] = av[2] = av[3] = R(0);
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const int lm = d == 0 ? Gm::lds(m, j, k) : (d == 1 ? Gm::lds(i, m, k) : Gm::lds(i, j, m));
+    const R Dim = sD[idx * Gm::DS + m];
+    const V2 f01 = sfv[0][lm], f23 = sfv[1][lm];
+    av[0] += Dim * f01.x;
+    av[1] += Dim * f01.y;
+    av[2] += Dim * f23.x;
+    av[3] += Dim * f23.y;
   }
 }
 
@@ -925,18 +989,44 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     __syncthreads();
   }
 
-  // ---- P2: lifted gradients --------------------------------------------
+  // ---- P2: lifted gradients ------------------------------------------------
+  // Kennedy-Gruber pair: one pass per line direction gives the lifted
+  // gradients and the convective flux differencing together; P3 then sweeps
+  // the viscous fluxes only.  Entropy-conserving pair: the lifted gradients
+  // here, the whole flux differencing in P3.
   R tau[6], qT[3];
 #pragma unroll
   for (int c = 0; c < 6; ++c) tau[c] = R(0);
   qT[0] = qT[1] = qT[2] = R(0);
-  if (VISC) {
+  double ut[5];
+  if constexpr (!EC) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ut[v] = 0.0;
     if (active) {
       R g[12];
-      lifted_gradients_half<N, R, V2, !EC>(sD, sp[le], sT, ssq[le], i, j, k,
-                                      static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
-                                      static_cast<R>(mesh.s[2][ez]), g);
-      if (ph.suth) {  // sT holds T - T_ref (T_ref = 0 in FP64)
+      fused_direction<N, R, 0, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sT, ssq[le], mesh.s[0][ex],
+                                                e_ref, p_ref, g, ut);
+      fused_direction<N, R, 1, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sT, ssq[le], mesh.s[1][ey],
+                                                e_ref, p_ref, g, ut);
+      fused_direction<N, R, 2, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sT, ssq[le], mesh.s[2][ez],
+                                                e_ref, p_ref, g, ut);
+      if (VISC) {
+        if (ph.suth) {  // sT holds T - T_ref (T_ref = 0 in FP64)
+          const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(sT[l]) + T_ref));
+          stress<R>(g, mu * r, kappa * r, tau, qT);
+        } else {
+          stress<R>(g, mu, kappa, tau, qT);
+        }
+      }
+    }
+    if (VISC) __syncthreads();
+  } else if (VISC) {
+    if (active) {
+      R g[12];
+      lifted_gradients_half<N, R, V2, false>(sD, sp[le], sT, ssq[le], i, j, k,
+                                             static_cast<R>(mesh.s[0][ex]), static_cast<R>(mesh.s[1][ey]),
+                                             static_cast<R>(mesh.s[2][ez]), g);
+      if (ph.suth) {
         const R r = static_cast<R>(viscosity_ratio(ph, static_cast<double>(sT[l]) + T_ref));
         stress<R>(g, mu * r, kappa * r, tau, qT);
       } else {
@@ -945,10 +1035,20 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     }
     __syncthreads();
   }
+  if constexpr (EC) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) ut[v] = 0.0;
+  }
 
   // ---- P3: line sweeps -------------------------------------------------
-  double ut[5] = {0, 0, 0, 0, 0};
-
+  // G of the RK update (node lanes) and the neighbour's face viscous flux
+  // (face lanes) are fetched before the last sweep and first used in P4/P5,
+  // so that their latency overlaps it.  The entropy-conserving instances,
+  // whose sweeps hold more registers, and the two-element workgroups fetch
+  // G after P3 and the face flux in P4.
+  constexpr bool EARLY = !EC && EPB == 1;
+  double gA[5] = {0, 0, 0, 0, 0};
+  double fvn_pre[4] = {0, 0, 0, 0};
 #define DG_DIRECTION(D)                                                                     \
   {                                                                                         \
     const int idx = D == 0 ? i : (D == 1 ? j : k);                                          \
@@ -963,40 +1063,50 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       if (idx == N)                                                                         \
         _Pragma("unroll") for (int c = 0; c < 4; ++c) sX[le][2 * D + 1][c][ab] = fv[c];     \
     }                                                                                       \
+    if constexpr (D == 2 && EARLY) {                                                        \
+      if (RK && active && st.read_G) load_state(out, stride, e * NN + node, gA);            \
+      if (VISC && face_ok && !fwall) {                                                      \
+        const FaceTask<N> ft(tid);                                                          \
+        const long long nb = neighbour(mesh, ex0, ey0, ez0, ft.d, ft.up);                   \
+        const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;             \
+        _Pragma("unroll") for (int c = 0; c < 4; ++c) fvn_pre[c] = static_cast<double>(src[c * NF]); \
+      }                                                                                     \
+    }                                                                                       \
     __syncthreads();                                                                        \
     if (active) {                                                                           \
-      R ac[5], av[4], du = R(0);                                                            \
-      if constexpr (EC && MIXED)                                                            \
-        volume_sweep_ec_mixed<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le],                \
-                                          static_cast<float>(0.5 / ph.gm1),                \
-                                          static_cast<float>(beta_ref),                    \
-                                          static_cast<float>(1.0 / beta_ref), ac, av, du); \
-      else if constexpr (EC)                                                                \
-        volume_sweep_ec<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le], ph.gm1, ac, av);     \
-      else                                                                                  \
-        volume_sweep<N, R, D, VISC, MIXED, V2>(own, i, j, k, sD, sp[le], sfv[le], ac, av, du); \
       const double sd = mesh.s[D][D == 0 ? ex : (D == 1 ? ey : ez)];                         \
-      ut[0] -= sd * static_cast<double>(R(2) * ac[0]);                                      \
-      _Pragma("unroll") for (int c = 0; c < 4; ++c)                                         \
-          ut[1 + c] -= sd * static_cast<double>(R(2) * ac[1 + c] - av[c]);                  \
-      if (MIXED)                                                                            \
-        ut[4] -= sd * 2.0 * (e_ref * static_cast<double>(ac[0]) +                           \
-                             p_ref * static_cast<double>(du));                              \
+      if constexpr (!EC) {                                                                  \
+        R av[4];                                                                            \
+        viscous_sweep<N, R, D, V2>(i, j, k, sD, sfv[le], av);                               \
+        _Pragma("unroll") for (int c = 0; c < 4; ++c) ut[1 + c] += sd * static_cast<double>(av[c]); \
+      } else {                                                                              \
+        R ac[5], av[4], du = R(0);                                                          \
+        if constexpr (MIXED)                                                                \
+          volume_sweep_ec_mixed<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le],              \
+                                            static_cast<float>(0.5 / ph.gm1),              \
+                                            static_cast<float>(beta_ref),                  \
+                                            static_cast<float>(1.0 / beta_ref), ac, av, du); \
+        else                                                                                \
+          volume_sweep_ec<N, D, VISC>(own, i, j, k, sD, sp[le], sfv[le], ph.gm1, ac, av);   \
+        ut[0] -= sd * static_cast<double>(R(2) * ac[0]);                                    \
+        _Pragma("unroll") for (int c = 0; c < 4; ++c)                                       \
+            ut[1 + c] -= sd * static_cast<double>(R(2) * ac[1 + c] - av[c]);                \
+        if (MIXED)                                                                          \
+          ut[4] -= sd * 2.0 * (e_ref * static_cast<double>(ac[0]) +                         \
+                               p_ref * static_cast<double>(du));                            \
+      }                                                                                     \
     }                                                                                       \
     __syncthreads();                                                                        \
   }
-  DG_DIRECTION(0)
-  DG_DIRECTION(1)
-  DG_DIRECTION(2)
+  if (EC || VISC) {
+    DG_DIRECTION(0)
+    DG_DIRECTION(1)
+    DG_DIRECTION(2)
+  }
 #undef DG_DIRECTION
 
-  // G of the RK update is fetched now and first used in P5, so that its
-  // latency overlaps P4
-  double gA[5] = {0, 0, 0, 0, 0};
-  if (RK && active && st.read_G) {
-    const long long gi = e * NN + node;
-#pragma unroll
-    for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + gi];
+  if (!EARLY || !VISC) {  // (Euler with the Kennedy-Gruber pair: no sweeps in P3)
+    if (RK && active && st.read_G) load_state(out, stride, e * NN + node, gA);
   }
 
   // ---- P4: surface corrections (face lanes, FP64) -----------------------
@@ -1006,8 +1116,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     int fx = ex0, fy = ey0, fz = ez0;
     if (EPB > 1) elem_coords(te, mesh, fx, fy, fz);
     const long long nb = neighbour(mesh, fx, fy, fz, ft.d, ft.up);
-    double fvo[4] = {0, 0, 0, 0}, fvn[4] = {0, 0, 0, 0};
-    if (VISC && !fwall) {
+    double fvo[4] = {0, 0, 0, 0}, fvn[4] = {fvn_pre[0], fvn_pre[1], fvn_pre[2], fvn_pre[3]};
+    if (!EARLY && VISC && !fwall) {
       const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
 #pragma unroll
       for (int c = 0; c < 4; ++c) fvn[c] = static_cast<double>(src[c * NF]);
@@ -1094,16 +1204,21 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   // ---- P5: surface terms, scaling, output -------------------------------
   if (active) {
     const double sx = mesh.s[0][ex], sy = mesh.s[1][ey], sz = mesh.s[2][ez];
+    // a node lies on at most one face per direction: one branch each
+    if (i == 0 || i == N) {
+      const int f = i == 0 ? 0 : 1;
 #pragma unroll
-    for (int v = 0; v < 5; ++v) {
-      double c = 0.0;
-      if (i == 0) c += sx * static_cast<double>(sX[le][0][v][j + NP * k]);
-      if (i == N) c += sx * static_cast<double>(sX[le][1][v][j + NP * k]);
-      if (j == 0) c += sy * static_cast<double>(sX[le][2][v][i + NP * k]);
-      if (j == N) c += sy * static_cast<double>(sX[le][3][v][i + NP * k]);
-      if (k == 0) c += sz * static_cast<double>(sX[le][4][v][i + NP * j]);
-      if (k == N) c += sz * static_cast<double>(sX[le][5][v][i + NP * j]);
-      ut[v] -= c;
+      for (int v = 0; v < 5; ++v) ut[v] -= sx * static_cast<double>(sX[le][f][v][j + NP * k]);
+    }
+    if (j == 0 || j == N) {
+      const int f = j == 0 ? 2 : 3;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) ut[v] -= sy * static_cast<double>(sX[le][f][v][i + NP * k]);
+    }
+    if (k == 0 || k == N) {
+      const int f = k == 0 ? 4 : 5;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) ut[v] -= sz * static_cast<double>(sX[le][f][v][i + NP * j]);
     }
     const long long idx = e * NN + node;
     if (RK) {

@@ -131,6 +131,9 @@ WORKLOADS = {
     # the same on curved elements: the periodic box warped by 5 % of its size
     "tgv_n7_32x32x32_curved": Workload("tgv_n7_32x32x32_curved", "tgv", 7, (32, 32, 32), nsteps=100,
                                        noise=0.01, seed=TGV_SEED, warp=0.05),
+    # the paper's throughput workload: a uniform free stream in the periodic
+    # box at N = 7 (its throughput does not depend on the solution)
+    "freestream_n7_32x32x32": Workload("freestream_n7_32x32x32", "freestream", 7, (32, 32, 32), nsteps=100),
     # small curved Taylor-Green case for full oracle comparisons
     "tgv_n3_4x4x4_curved": Workload("tgv_n3_4x4x4_curved", "tgv", 3, (4, 4, 4), nsteps=10, warp=0.05),
     # stretched channel for the adjoint: N=5, 16^3 elements, 50 steps
