@@ -178,6 +178,25 @@ dg_status dg_get_state(const dg_ctx* ctx, double* U_dev);
  * t is the physical time (the operator has no time-dependent terms).       */
 dg_status dg_eval_rhs(dg_ctx* ctx, const double* U_dev, double* Ut_dev, double t);
 
+/* Allocation-free dg_eval_rhs, for callers that cannot allocate device
+ * memory or bind a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Ut = L(U) by the same kernels in
+ * the same order as dg_eval_rhs (bitwise the same result); the derivative
+ * matrix, the element scale tables, the face viscous fluxes, the wall-model
+ * stress and the status word live in a static device array of the library,
+ * 64 MiB per device, instead of the workspace, and the call allocates
+ * nothing.  The context needs no workspace (one from dg_init_mesh alone
+ * works).  U and Ut: device arrays of 5 n_dof doubles in the state layout,
+ * caller owned, not overlapping.  status_dev: a device int that a
+ * non-physical state sets to 1 (the caller clears it), or NULL to drop that
+ * report.  Every call on a device rewrites that device's array: calls that
+ * overlap on one device race (one stream at a time).  Errors: DG_EINVAL (null
+ * pointers; a mesh whose face fluxes and tables exceed the 64 MiB: at N = 7
+ * about 5,400 elements in FP64, 10,900 in mixed precision), DG_EUNSUPPORTED
+ * (curved elements), DG_EHIP.                                                */
+dg_status dg_eval_rhs_noalloc(dg_ctx* ctx, const double* U_dev, double* Ut_dev, double t,
+                              int* status_dev);
+
 /* BR1 lifted gradients of (u, v, w, T) of U, layout above (FP64 contexts only). */
 dg_status dg_eval_lift(dg_ctx* ctx, const double* U_dev, double* grad_dev);
 

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgsem.so")
 SOURCES = ["api.cpp", "lgl.cpp", "fwd_kernels.hip", "lift_kernels.hip", "aux_kernels.hip",
-           "adj_kernels.hip", "wall_kernels.hip", "curv_kernels.hip"]
+           "adj_kernels.hip", "wall_kernels.hip", "curv_kernels.hip", "noalloc.hip"]
 
 ARCH = os.environ.get("DGSEM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

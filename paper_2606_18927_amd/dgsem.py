@@ -61,6 +61,7 @@ _SIGNATURES = {
     "dg_set_state": (_I, [_P, _P]),
     "dg_get_state": (_I, [_P, _P]),
     "dg_eval_rhs": (_I, [_P, _P, _P, _D]),
+    "dg_eval_rhs_noalloc": (_I, [_P, _P, _P, _D, _P]),
     "dg_eval_lift": (_I, [_P, _P, _P]),
     "dg_rk_step": (_I, [_P, _D, _D, _I]),
     "dg_rk_graph_build": (_I, [_P, _D, _I]),
@@ -226,6 +227,21 @@ class Solver:
         out = self.state_like() if out is None else out
         self._check(lib().dg_eval_rhs(self._ctx, self._state_ptr(U), self._state_ptr(out, "Ut"), t),
                     "dg_eval_rhs")
+        return out
+
+    def eval_rhs_noalloc(self, U: torch.Tensor, out: torch.Tensor | None = None, t: float = 0.0,
+                         status: torch.Tensor | None = None) -> torch.Tensor:
+        """dg_eval_rhs_noalloc: the right-hand side with the library's static
+        device scratch instead of the workspace; `status` (a one-element int32
+        CUDA tensor, optional) is set to 1 by a non-physical state."""
+        out = self.state_like() if out is None else out
+        sptr = 0
+        if status is not None:
+            if not status.is_cuda or status.dtype != torch.int32 or status.numel() < 1:
+                raise ValueError("status: expected an int32 CUDA tensor")
+            sptr = status.data_ptr()
+        self._check(lib().dg_eval_rhs_noalloc(self._ctx, self._state_ptr(U), self._state_ptr(out, "Ut"), t, sptr),
+                    "dg_eval_rhs_noalloc")
         return out
 
     def eval_lift(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
