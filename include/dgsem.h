@@ -26,8 +26,10 @@
  *     returns a dg_status; no exception crosses the ABI.  Device-side
  *     failures (non-positive density or pressure, NaN) are reported by dg_sync.
  *   - The library never allocates device memory: the caller provides the
- *     workspace (dg_workspace_bytes, dg_bind_workspace).  A context is bound
- *     to one stream and one device and is not thread-safe.
+ *     workspace (dg_workspace_bytes, dg_bind_workspace); the one exception is
+ *     the static 64 MiB device array of dg_eval_rhs_noalloc, which exists per
+ *     device with the loaded library.  A context is bound to one stream and
+ *     one device and is not thread-safe.
  */
 #ifndef DGSEM_H
 #define DGSEM_H
@@ -117,10 +119,13 @@ typedef struct {
 typedef struct {
   double gamma, R, mu, Pr;
   int viscous;        /* 0: Euler fluxes only (no lifting), 1: Navier-Stokes      */
-  int precision;      /* DG_FP64, or DG_MIXED: FP32 lifting, volume fluxes and
-                         line sums; FP64 state, primitive recovery, surface
-                         fluxes and RK accumulation; p, e and T enter the FP32
-                         parts relative to a per-element reference value       */
+  int precision;      /* DG_FP64, or DG_MIXED: FP32 lifting, volume fluxes,
+                         line sums and Lax-Friedrichs surface fluxes; FP64
+                         state, primitive recovery, lifting corrections, the
+                         Roe surface flux and RK accumulation; p, e and T enter
+                         the FP32 parts relative to a per-element reference
+                         value (the surface fluxes as FP64 differences of the
+                         two sides)                                            */
   int central_only;   /* 1: drop the surface dissipation (Lax-Friedrichs or Roe):
                          test switch                                             */
   int flux;           /* DG_FLUX_KG_LLF or DG_FLUX_EC_ROE                          */

@@ -26,8 +26,10 @@
 //   P5  node lanes add them, scale by s_d = 2/width_d and write or update.
 //
 // Mixed precision (R = float): the LDS fields, gradients, viscous fluxes and
-// line sums are FP32; U, G, the primitive recovery, the surface fluxes and the
-// RK update stay FP64.  Pressure, specific energy and temperature are stored
+// line sums are FP32, and so are the Lax-Friedrichs surface fluxes (formed
+// from FP64 differences of the two sides' states); U, G, the primitive
+// recovery, the lifting corrections, the Roe surface flux of the
+// entropy-conserving pair and the RK update stay FP64.  Pressure, specific energy and temperature are stored
 // relative to the element's first node (p - p_ref, e - e_ref, T - T_ref, with
 // the differences taken in FP64), and the exactly known contributions of the
 // reference values are added back: sum_m D_im = 0 removes p_ref from the
@@ -588,6 +590,70 @@ __device__ inline void surface_correction(const double A[6], const double so[5],
     for (int c = 0; c < 4; ++c) corr[1 + c] -= 0.5 * (fvo[c] + fvn[c]);
   }
   const double sc = up ? inv_w : -inv_w;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) corr[v] *= sc;
+}
+
+// Surface correction of one face task in FP32 (mixed precision, Kennedy-Gruber
+// / Lax-Friedrichs pair): the terms of surface_correction written in the
+// differences dx = x_n - x_o of the neighbour's and the own primitives
+// (formed in FP64 from the FP64 states, then rounded once), so that no FP32
+// difference of large, nearly equal values is formed (p ~ 70, e ~ 180 at
+// Ma = 0.1).  With m_o = rho_o u_d,o and dm = {{rho}}{{u_d}} - m_o
+// = (drho/2) u_d,o + {{rho}} (du_d/2), exactly:
+//   f#_d - f_d(own):  mass dm;  momentum a: dm {{u_a}} + m_o du_a/2 + e_ad dp/2;
+//                     energy dm {{e}} + m_o de/2 + {{u_d}} dp/2 + p_o du_d/2;
+// the dissipation -lambda/2 (U_R - U_L) from the FP64 differences of the
+// conservative states; the BR1 viscous part (f_v,o - f_v,n)/2.  A wall face
+// keeps the pressure-only convective flux and the zero-velocity viscous flux
+// (own stresses; of the energy flux only the heat flux).
+template <int d>
+__device__ inline void surface_correction_f32(const Prim& Po, const double so[5], const double sn[5],
+                                              bool wall, bool up, const double fvo[4], const double fvn[4],
+                                              const DevPhys& ph, double inv_w, float corr[5]) {
+  const float uo[3] = {static_cast<float>(Po.u), static_cast<float>(Po.v), static_cast<float>(Po.w)};
+  const float ro = static_cast<float>(Po.rho);
+  const float mo = ro * uo[d];
+  if (wall) {
+    corr[0] = -mo;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) corr[1 + a] = -mo * uo[a];
+    corr[4] = -static_cast<float>(so[4] + Po.p) * uo[d] +
+              (uo[0] * static_cast<float>(fvo[0]) + uo[1] * static_cast<float>(fvo[1]) +
+               uo[2] * static_cast<float>(fvo[2]));
+  } else {
+    const double irn = 1.0 / sn[0];
+    const double un[3] = {sn[1] * irn, sn[2] * irn, sn[3] * irn};
+    const double pn = ph.gm1 * (sn[4] - 0.5 * sn[0] * (un[0] * un[0] + un[1] * un[1] + un[2] * un[2]));
+    const float h = 0.5f;
+    const float hdr = h * static_cast<float>(sn[0] - Po.rho);
+    const float hdu[3] = {h * static_cast<float>(un[0] - Po.u), h * static_cast<float>(un[1] - Po.v),
+                          h * static_cast<float>(un[2] - Po.w)};
+    const float hdp = h * static_cast<float>(pn - Po.p);
+    const float hde = h * static_cast<float>(sn[4] * irn - Po.e);
+    const float rm = ro + hdr;
+    float um[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) um[a] = uo[a] + hdu[a];
+    const float dm = hdr * uo[d] + rm * hdu[d];
+    corr[0] = dm;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) corr[1 + a] = dm * um[a] + mo * hdu[a];
+    corr[1 + d] += hdp;
+    corr[4] = dm * (static_cast<float>(Po.e) + hde) + mo * hde + um[d] * hdp + static_cast<float>(Po.p) * hdu[d];
+    if (!ph.central) {
+      const float gam = static_cast<float>(ph.gamma);
+      const float cu = fabsf(uo[d]) + sqrtf(gam * static_cast<float>(Po.p) / ro);
+      const float cn = fabsf(static_cast<float>(un[d])) + sqrtf(gam * static_cast<float>(pn * irn));
+      const float lam = cu >= cn ? cu : cn;
+      const float sl = (up ? -0.5f : 0.5f) * lam;
+#pragma unroll
+      for (int v = 0; v < 5; ++v) corr[v] += sl * static_cast<float>(sn[v] - so[v]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) corr[1 + c] += h * static_cast<float>(fvo[c] - fvn[c]);
+  }
+  const float sc = static_cast<float>(up ? inv_w : -inv_w);
 #pragma unroll
   for (int v = 0; v < 5; ++v) corr[v] *= sc;
 }
@@ -1182,6 +1248,15 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
       if (ft.d == 0) surface_correction_ec<0>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
       if (ft.d == 1) surface_correction_ec<1>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
       if (ft.d == 2) surface_correction_ec<2>(A, q2o, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
+    } else if constexpr (MIXED) {
+      // mixed precision: the surface fluxes in FP32 from FP64 differences
+      const Prim Po = primitives(so, ph);
+      float c32[5];
+      if (ft.d == 0) surface_correction_f32<0>(Po, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, c32);
+      if (ft.d == 1) surface_correction_f32<1>(Po, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, c32);
+      if (ft.d == 2) surface_correction_f32<2>(Po, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, c32);
+#pragma unroll
+      for (int v = 0; v < 5; ++v) corr[v] = c32[v];
     } else {
       if (ft.d == 0) surface_correction<0>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
       if (ft.d == 1) surface_correction<1>(A, so, sn, fwall, ft.up, fvo, fvn, ph, basis.inv_w_end, corr);
