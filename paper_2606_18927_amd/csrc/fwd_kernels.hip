@@ -1162,8 +1162,12 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
                                p_ref * static_cast<double>(du));                            \
       }                                                                                     \
     }                                                                                       \
-    __syncthreads();                                                                        \
+    if constexpr (D < 2) __syncthreads();                                                   \
   }
+  // No barrier after the last sweep: P4 reads the own face states (sp, sN,
+  // sO) and the own face viscous fluxes stored before that sweep's barrier,
+  // and overwrites only its own face entries of sX, which no sweep reads, so
+  // each wave goes on to its surface terms as soon as its sweep is done.
   if (EC || VISC) {
     DG_DIRECTION(0)
     DG_DIRECTION(1)
