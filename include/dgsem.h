@@ -109,7 +109,8 @@ typedef struct {
                          entropy-conserving pair, the wall model and the
                          adjoint, lifting or kinetic-energy calls give
                          DG_EUNSUPPORTED.  The workspace holds the metric
-                         terms, 10 FP64 + 10 FP32 values per DOF.  A non-positive Jacobian at any node
+                         terms, 10 FP64 values per DOF (+ 10 FP32 values in
+                         mixed precision).  A non-positive Jacobian at any node
                          makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;
 

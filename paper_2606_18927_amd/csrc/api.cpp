@@ -85,7 +85,10 @@ Layout layout(const dg_ctx* c) {
   L.G = take(state);
   L.ffv = c->phys.viscous ? take(fbytes) : off;
   L.tauw = c->wall_model ? take(static_cast<size_t>(c->n_wall_faces) * 3 * NP * NP * sizeof(double)) : off;
-  L.geo = c->curvilinear ? take(10 * dof * (sizeof(double) + sizeof(float))) : off;  // FP64 + FP32 copy
+  // FP64 metric terms, and their FP32 copy for the mixed-precision sweeps
+  L.geo = c->curvilinear
+              ? take(10 * dof * (sizeof(double) + (c->phys.precision == DG_FP64 ? 0 : sizeof(float))))
+              : off;
   L.fwd_end = off;
   L.stages = take(5 * state);
   L.lamG = take(state);
@@ -456,7 +459,8 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
     if ((st = hip_check(c, hipMemcpyAsync(c->G, c->nodes.data(), xbytes, hipMemcpyHostToDevice, c->stream),
                         "upload nodes")) != DG_OK)
       return st;
-    if ((st = hip_check(c, dg::launch_metrics(c->N, c->G, c->geo, dev_basis(c), c->nE, c->dstatus, c->stream),
+    if ((st = hip_check(c, dg::launch_metrics(c->N, c->G, c->geo, c->phys.precision != DG_FP64, dev_basis(c), c->nE,
+                                             c->dstatus, c->stream),
                         "metrics kernel")) != DG_OK)
       return st;
     int bad = 0;

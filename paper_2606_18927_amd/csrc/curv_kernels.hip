@@ -118,8 +118,9 @@ __device__ inline void roe_dissipation_normal(const double L[5], double EL, cons
 // ---------------------------------------------------------------- metrics
 template <int N>
 __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __restrict__ X,
-                                                           double* __restrict__ geo, DevBasis basis,
-                                                           long long nE, int* __restrict__ status) {
+                                                           double* __restrict__ geo, bool with_f32,
+                                                           DevBasis basis, long long nE,
+                                                           int* __restrict__ status) {
   using C = CurvCfg<N>;
   constexpr int NP = C::NP, NN = C::NN;
   __shared__ double sD[NP][N + 2];
@@ -179,10 +180,13 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __rest
     for (int c = 0; c < 9; ++c) geo[c * stride + o] = Ja[c];
     geo[9 * stride + o] = 1.0 / J;
     // FP32 copy for the mixed-precision sweeps, after the ten FP64 fields
-    float* const g32 = reinterpret_cast<float*>(geo + 10 * stride);
+    // (the workspace holds it only in mixed-precision contexts)
+    if (with_f32) {
+      float* const g32 = reinterpret_cast<float*>(geo + 10 * stride);
 #pragma unroll
-    for (int c = 0; c < 9; ++c) g32[c * stride + o] = static_cast<float>(Ja[c]);
-    g32[9 * stride + o] = static_cast<float>(1.0 / J);
+      for (int c = 0; c < 9; ++c) g32[c * stride + o] = static_cast<float>(Ja[c]);
+      g32[9 * stride + o] = static_cast<float>(1.0 / J);
+    }
   }
 }
 
@@ -740,10 +744,10 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
 }
 
 template <int N>
-hipError_t metrics_n(const double* X, double* geo, const DevBasis& b, long long nE, int* status,
-                     hipStream_t s) {
-  hipLaunchKernelGGL((k_metrics<N>), dim3(static_cast<unsigned>(nE)), dim3(CurvCfg<N>::BS), 0, s, X, geo, b,
-                     nE, status);
+hipError_t metrics_n(const double* X, double* geo, bool with_f32, const DevBasis& b, long long nE,
+                     int* status, hipStream_t s) {
+  hipLaunchKernelGGL((k_metrics<N>), dim3(static_cast<unsigned>(nE)), dim3(CurvCfg<N>::BS), 0, s, X, geo,
+                     with_f32, b, nE, status);
   return hipGetLastError();
 }
 
@@ -797,12 +801,12 @@ hipError_t rhs_curv_dispatch(int N, const DevMesh& m, const DevPhys& p, const De
 
 }  // namespace
 
-hipError_t launch_metrics(int N, const double* X, double* geo, const DevBasis& b, long long nE,
-                          int* status, hipStream_t s) {
+hipError_t launch_metrics(int N, const double* X, double* geo, bool with_f32, const DevBasis& b,
+                          long long nE, int* status, hipStream_t s) {
   switch (N) {
-    case 3: return metrics_n<3>(X, geo, b, nE, status, s);
-    case 5: return metrics_n<5>(X, geo, b, nE, status, s);
-    case 7: return metrics_n<7>(X, geo, b, nE, status, s);
+    case 3: return metrics_n<3>(X, geo, with_f32, b, nE, status, s);
+    case 5: return metrics_n<5>(X, geo, with_f32, b, nE, status, s);
+    case 7: return metrics_n<7>(X, geo, with_f32, b, nE, status, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -81,11 +81,12 @@ hipError_t launch_rhs_vjp(int N, const DevMesh& m, const DevPhys& p, const DevBa
 hipError_t launch_axpby(double* y, const double* x, double a, double b, long long n, hipStream_t s);
 
 // Curvilinear hexahedra (curv_kernels.hip): metric terms from the node
-// coordinates X[n][e][node] (status[0] = 1 where J <= 0), and the operator
+// coordinates X[n][e][node] (status[0] = 1 where J <= 0; with_f32: also
+// their FP32 copy after the ten FP64 fields, for mixed precision), and the operator
 // (face viscous fluxes double*, or float* unless precision is DG_FP64; one RK
 // stage or the right-hand side alone).
-hipError_t launch_metrics(int N, const double* X, double* geo, const DevBasis& b, long long nE,
-                          int* status, hipStream_t s);
+hipError_t launch_metrics(int N, const double* X, double* geo, bool with_f32, const DevBasis& b,
+                          long long nE, int* status, hipStream_t s);
 hipError_t launch_face_flux_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
                                  const double* U, void* ffv, hipStream_t s);
 hipError_t launch_rhs_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,

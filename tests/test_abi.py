@@ -196,7 +196,14 @@ def test_curved_mesh_validation(L):
     d, keep = desc()
     st, ctx = _init(L, d, _phys(precision=1))  # mixed precision with the Kennedy-Gruber pair
     assert st == dgsem.DG_OK
+    mixed = ctypes.c_size_t()
+    assert L.dg_workspace_bytes(ctx, 0, ctypes.byref(mixed)) == dgsem.DG_OK
     L.dg_free(ctx)
+    # the FP32 copy of the metric terms (10 values per DOF) exists only in
+    # mixed precision, whose face fluxes are FP32 (half the FP64 ones)
+    ff64 = 8 * 6 * 4 * (N + 1) ** 2 * 8
+    assert mixed.value >= size.value + 10 * nd * 4 - ff64 // 2 - 4096
+    assert mixed.value <= size.value + 10 * nd * 4 + 4096
     for bad, code in ((dict(precision=1, flux=1), dgsem.DG_EUNSUPPORTED),):
         d, keep = desc()
         assert _init(L, d, _phys(**bad))[0] == code, bad
