@@ -110,7 +110,8 @@ typedef struct {
                          adjoint, lifting or kinetic-energy calls give
                          DG_EUNSUPPORTED.  The workspace holds the metric
                          terms, 10 FP64 values per DOF (+ 10 FP32 values in
-                         mixed precision).  A non-positive Jacobian at any node
+                         mixed precision) and the FP64 ones again per node
+                         on the element boundary.  A non-positive Jacobian at any node
                          makes dg_bind_workspace fail with DG_EINVAL.          */
 } dg_mesh_desc;
 

@@ -57,7 +57,7 @@ dg_status hip_check(dg_ctx* c, hipError_t e, const char* what) {
 }
 
 struct Layout {
-  size_t D, w, s[3], status, partial, U0, U1, G, ffv, tauw, geo;
+  size_t D, w, s[3], status, partial, U0, U1, G, ffv, tauw, geo, geoF;
   size_t stages, lamG, lamU, ubar, gbar, tmp;
   size_t fwd_end, adj_end;
 };
@@ -89,6 +89,11 @@ Layout layout(const dg_ctx* c) {
   L.geo = c->curvilinear
               ? take(10 * dof * (sizeof(double) + (c->phys.precision == DG_FP64 ? 0 : sizeof(float))))
               : off;
+  // the ten FP64 fields once more at the boundary nodes, contiguous per element
+  // for the face-flux kernel and the surface terms
+  L.geoF = c->curvilinear
+               ? take(10 * static_cast<size_t>(c->nE) * dg::face_nodes_per_element(c->N) * sizeof(double))
+               : off;
   L.fwd_end = off;
   L.stages = take(5 * state);
   L.lamG = take(state);
@@ -111,6 +116,7 @@ dg::DevMesh dev_mesh(const dg_ctx* c) {
   m.nE = c->nE;
   m.tauw = c->wall_model ? c->tauw : nullptr;
   m.geo = c->curvilinear ? c->geo : nullptr;
+  m.geoF = c->curvilinear ? c->geoF : nullptr;
   return m;
 }
 
@@ -425,6 +431,7 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
   c->ffv = c->phys.viscous ? static_cast<void*>(ws + L.ffv) : nullptr;
   c->tauw = c->wall_model ? reinterpret_cast<double*>(ws + L.tauw) : nullptr;
   c->geo = c->curvilinear ? reinterpret_cast<double*>(ws + L.geo) : nullptr;
+  c->geoF = c->curvilinear ? reinterpret_cast<double*>(ws + L.geoF) : nullptr;
   if (with_adjoint) {
     c->stages = reinterpret_cast<double*>(ws + L.stages);
     c->lamG = reinterpret_cast<double*>(ws + L.lamG);
@@ -459,8 +466,8 @@ dg_status dg_bind_workspace(dg_ctx* c, void* dev_ptr, size_t bytes, int with_adj
     if ((st = hip_check(c, hipMemcpyAsync(c->G, c->nodes.data(), xbytes, hipMemcpyHostToDevice, c->stream),
                         "upload nodes")) != DG_OK)
       return st;
-    if ((st = hip_check(c, dg::launch_metrics(c->N, c->G, c->geo, c->phys.precision != DG_FP64, dev_basis(c), c->nE,
-                                             c->dstatus, c->stream),
+    if ((st = hip_check(c, dg::launch_metrics(c->N, c->G, c->geo, c->geoF, c->phys.precision != DG_FP64,
+                                             dev_basis(c), c->nE, c->dstatus, c->stream),
                         "metrics kernel")) != DG_OK)
       return st;
     int bad = 0;

@@ -118,7 +118,8 @@ __device__ inline void roe_dissipation_normal(const double L[5], double EL, cons
 // ---------------------------------------------------------------- metrics
 template <int N>
 __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __restrict__ X,
-                                                           double* __restrict__ geo, bool with_f32,
+                                                           double* __restrict__ geo,
+                                                           double* __restrict__ geoF, bool with_f32,
                                                            DevBasis basis, long long nE,
                                                            int* __restrict__ status) {
   using C = CurvCfg<N>;
@@ -179,6 +180,14 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_metrics(const double* __rest
 #pragma unroll
     for (int c = 0; c < 9; ++c) geo[c * stride + o] = Ja[c];
     geo[9 * stride + o] = 1.0 / J;
+    // boundary nodes once more, contiguous per element (face node number t)
+    if (i == 0 || i == N || j == 0 || j == N || k == 0 || k == N) {
+      constexpr int NFN = n_face_nodes<N>();
+      const long long of = e * NFN + face_node_index<N>(i, j, k);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) geoF[c * nE * NFN + of] = Ja[c];
+      geoF[9 * nE * NFN + of] = 1.0 / J;
+    }
     // FP32 copy for the mixed-precision sweeps, after the ten FP64 fields
     // (the workspace holds it only in mixed-precision contexts)
     if (with_f32) {
@@ -241,13 +250,6 @@ __device__ inline void curv_gradients(const R* const sq[4], const double (*sD)[N
   }
 }
 
-__device__ inline void load_geo(const double* geo, long long stride, long long idx, double Ja[9],
-                                double& invJ) {
-#pragma unroll
-  for (int c = 0; c < 9; ++c) Ja[c] = geo[c * stride + idx];
-  invJ = geo[9 * stride + idx];
-}
-
 // Metric field c at node idx in the sweep precision: the FP64 field, or its
 // FP32 copy stored after the ten FP64 fields.
 template <typename R>
@@ -276,6 +278,15 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
   int ex, ey, ez;
   elem_coords(e, mesh, ex, ey, ez);
   if (tid < NP * NP) sD[tid / NP][tid % NP] = basis.D[tid];
+  constexpr int NFN = n_face_nodes<N>();
+  static_assert(NFN <= CurvCfg<N>::BS, "one lane per boundary node");
+  double Ja[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, invJ = 0.0;
+  if (tid < NFN) {
+    const long long fs = nE * NFN, of = e * NFN + tid;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) Ja[c] = mesh.geoF[c * fs + of];
+    invJ = mesh.geoF[9 * fs + of];
+  }
   if (tid < NN) {
     double s[5];
     load_state(U, stride, e * NN + tid, s);
@@ -312,19 +323,19 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
     for (int c = 0; c < 4; ++c) corr[ft.f][c][ft.ab] = (qs[c] - qo[c]) * sc;
   }
   __syncthreads();
-  if (tid >= NN) return;
-  const int i = tid % NP, j = (tid / NP) % NP, k = tid / NF;
-  const bool on_face = i == 0 || i == N || j == 0 || j == N || k == 0 || k == N;
-  if (!on_face) return;
-  double Ja[9], invJ;
-  load_geo(mesh.geo, stride, e * NN + tid, Ja, invJ);
+  // one lane per boundary node (face node number t = tid), with that node's
+  // metric terms from the boundary-node copy (fetched before the barriers)
+  if (tid >= NFN) return;
+  int i, j, k;
+  face_node_of<N>(tid, i, j, k);
+  const int n = i + NP * (j + NP * k);
   const double* const q[4] = {sq[0], sq[1], sq[2], sq[3]};
   double g[12];
   curv_gradients<N, double>(q, sD, corr, i, j, k, Ja, invJ, g);
-  const double r = viscosity_ratio(ph, sq[3][tid]);
+  const double r = viscosity_ratio(ph, sq[3][n]);
   double tau[6], qT[3];
   stress64<double>(g, ph.mu * r, ph.kappa * r, tau, qT);
-  const double u = sq[0][tid], v = sq[1][tid], w = sq[2][tid];
+  const double u = sq[0][n], v = sq[1][n], w = sq[2][n];
   R* out = ffv + e * (6 * 4 * NF);
   double f[4];
 #pragma unroll
@@ -582,9 +593,20 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     // (a wall face has no element on its other side: the own normal)
     const bool fwall = nb < 0;
     double s[3];
-    const long long gi = (ft.up || fwall) ? e * NN + lo : nb * NN + ft.nb_node();
+    const long long ge = (ft.up || fwall) ? e : nb;
+    const int gn = (ft.up || fwall) ? lo : ft.nb_node();
+    if constexpr (MIXED) {
+      // the sweeps read the FP32 copy, so the FP64 rows are not in L2 here:
+      // the boundary-node copy is the smaller fetch
+      constexpr int NFN = n_face_nodes<N>();
+      const long long gi = ge * NFN + face_node_index<N>(gn % NP, (gn / NP) % NP, gn / NF);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) s[c] = mesh.geo[(3 * ft.d + c) * stride + gi];
+      for (int c = 0; c < 3; ++c) s[c] = mesh.geoF[(3 * ft.d + c) * (nE * NFN) + gi];
+    } else {
+      // FP64: the gradient phase read these rows, mostly still in L2
+#pragma unroll
+      for (int c = 0; c < 3; ++c) s[c] = mesh.geo[(3 * ft.d + c) * stride + ge * NN + gn];
+    }
     // the neighbour's face node, fetched again (a state of its own, so that
     // the one of the lifting phase is not held through the sweeps)
     double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
@@ -744,10 +766,10 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
 }
 
 template <int N>
-hipError_t metrics_n(const double* X, double* geo, bool with_f32, const DevBasis& b, long long nE,
-                     int* status, hipStream_t s) {
+hipError_t metrics_n(const double* X, double* geo, double* geoF, bool with_f32, const DevBasis& b,
+                     long long nE, int* status, hipStream_t s) {
   hipLaunchKernelGGL((k_metrics<N>), dim3(static_cast<unsigned>(nE)), dim3(CurvCfg<N>::BS), 0, s, X, geo,
-                     with_f32, b, nE, status);
+                     geoF, with_f32, b, nE, status);
   return hipGetLastError();
 }
 
@@ -801,12 +823,12 @@ hipError_t rhs_curv_dispatch(int N, const DevMesh& m, const DevPhys& p, const De
 
 }  // namespace
 
-hipError_t launch_metrics(int N, const double* X, double* geo, bool with_f32, const DevBasis& b,
-                          long long nE, int* status, hipStream_t s) {
+hipError_t launch_metrics(int N, const double* X, double* geo, double* geoF, bool with_f32,
+                          const DevBasis& b, long long nE, int* status, hipStream_t s) {
   switch (N) {
-    case 3: return metrics_n<3>(X, geo, with_f32, b, nE, status, s);
-    case 5: return metrics_n<5>(X, geo, with_f32, b, nE, status, s);
-    case 7: return metrics_n<7>(X, geo, with_f32, b, nE, status, s);
+    case 3: return metrics_n<3>(X, geo, geoF, with_f32, b, nE, status, s);
+    case 5: return metrics_n<5>(X, geo, geoF, with_f32, b, nE, status, s);
+    case 7: return metrics_n<7>(X, geo, geoF, with_f32, b, nE, status, s);
     default: return hipErrorInvalidValue;
   }
 }

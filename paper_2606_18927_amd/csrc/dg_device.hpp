@@ -158,6 +158,47 @@ struct FaceTask {
   __device__ int own_node() const { return oi + (N + 1) * (oj + (N + 1) * ok); }
 };
 
+// Face node number t (0 <= t < n_face_nodes) of an element -> (i, j, k): the
+// two k planes first, then the boundary ring of each interior k plane.
+template <int N>
+__host__ __device__ inline void face_node_of(int t, int& i, int& j, int& k) {
+  constexpr int NP = N + 1, NF = NP * NP, RING = 4 * N;
+  if (t < 2 * NF) {
+    k = t < NF ? 0 : N;
+    const int ab = t < NF ? t : t - NF;
+    i = ab % NP;
+    j = ab / NP;
+    return;
+  }
+  const int r = t - 2 * NF;
+  k = 1 + r / RING;
+  const int q = r % RING;
+  if (q < NP) {
+    i = q; j = 0;
+  } else if (q < 2 * NP) {
+    i = q - NP; j = N;
+  } else if (q < 2 * NP + N - 1) {
+    i = 0; j = q - 2 * NP + 1;
+  } else {
+    i = N; j = q - (2 * NP + N - 1) + 1;
+  }
+}
+
+template <int N>
+__host__ __device__ constexpr int n_face_nodes() {
+  return 2 * (N + 1) * (N + 1) + (N - 1) * 4 * N;
+}
+
+// Inverse of face_node_of: the face node number of a node on the element's
+// boundary.
+template <int N>
+__host__ __device__ constexpr int face_node_index(int i, int j, int k) {
+  constexpr int NP = N + 1, NF = NP * NP, RING = 4 * N;
+  if (k == 0 || k == N) return (k == 0 ? 0 : NF) + i + NP * j;
+  const int q = j == 0 ? i : (j == N ? NP + i : (i == 0 ? 2 * NP + j - 1 : 2 * NP + N - 1 + j - 1));
+  return 2 * NF + (k - 1) * RING + q;
+}
+
 struct Prim {
   double rho, u, v, w, p, e, T;
 };

@@ -26,6 +26,8 @@ struct DevMesh {
   long long nE;       // number of elements
   const double* tauw; // wall-model stress per wall-face node (DG_BC_WALL_MODEL), or null
   const double* geo;  // curvilinear metrics geo[c][e][node] (c = 3 i + n: J a^i_n; 9: 1/J), or null
+  const double* geoF; // the same ten fields at the element's boundary nodes only,
+                      // geoF[c][e][t] (t: face node number), or null
 };
 
 // Gas constants and switches (FP64; kernels cast where they compute in FP32).
@@ -53,6 +55,8 @@ struct Stage {
 // Kernel launchers.  ffv (face viscous fluxes, face_flux_values_per_element
 // values per element) is double* for DG_FP64 and float* for DG_MIXED.
 inline size_t face_flux_values_per_element(int N) { return static_cast<size_t>(6 * 4 * (N + 1) * (N + 1)); }
+// nodes on an element's boundary: the two k planes and the ring of each interior one
+inline size_t face_nodes_per_element(int N) { return static_cast<size_t>(2 * (N + 1) * (N + 1) + (N - 1) * 4 * N); }
 hipError_t launch_face_flux(int N, int precision, const DevMesh& m, const DevPhys& p,
                             const DevBasis& b, const double* U, void* ffv, hipStream_t s);
 hipError_t launch_rhs(int N, int precision, const DevMesh& m, const DevPhys& p,
@@ -82,10 +86,11 @@ hipError_t launch_axpby(double* y, const double* x, double a, double b, long lon
 
 // Curvilinear hexahedra (curv_kernels.hip): metric terms from the node
 // coordinates X[n][e][node] (status[0] = 1 where J <= 0; with_f32: also
-// their FP32 copy after the ten FP64 fields, for mixed precision), and the operator
+// their FP32 copy after the ten FP64 fields, for mixed precision; geoF: the
+// FP64 fields of the boundary nodes, contiguous per element), and the operator
 // (face viscous fluxes double*, or float* unless precision is DG_FP64; one RK
 // stage or the right-hand side alone).
-hipError_t launch_metrics(int N, const double* X, double* geo, bool with_f32, const DevBasis& b,
+hipError_t launch_metrics(int N, const double* X, double* geo, double* geoF, bool with_f32, const DevBasis& b,
                           long long nE, int* status, hipStream_t s);
 hipError_t launch_face_flux_curv(int N, int precision, const DevMesh& m, const DevPhys& p, const DevBasis& b,
                                  const double* U, void* ffv, hipStream_t s);
@@ -131,6 +136,7 @@ struct dg_ctx {
   bool curvilinear = false;   // node coordinates given: curved elements
   std::vector<double> nodes;  // their host copy [n][e][node]
   double* geo = nullptr;      // metric terms (workspace)
+  double* geoF = nullptr;     // their boundary-node copy (workspace)
   long long n_wall_faces = 0;
   dg_physics phys{};
   hipStream_t stream = nullptr;

@@ -173,37 +173,6 @@ __device__ inline void element_ref(const double s0[5], const DevPhys& ph, double
 // --------------------------------------------------------------------------
 // k_face_flux: f_v,d on the face planes, layout ffv[e][face][c][ab]
 // --------------------------------------------------------------------------
-// Face node number t (0 <= t < n_face_nodes) of an element -> (i, j, k): the
-// two k planes first, then the boundary ring of each interior k plane.
-template <int N>
-__device__ inline void face_node_of(int t, int& i, int& j, int& k) {
-  constexpr int NP = N + 1, NF = NP * NP, RING = 4 * N;
-  if (t < 2 * NF) {
-    k = t < NF ? 0 : N;
-    const int ab = t < NF ? t : t - NF;
-    i = ab % NP;
-    j = ab / NP;
-    return;
-  }
-  const int r = t - 2 * NF;
-  k = 1 + r / RING;
-  const int q = r % RING;
-  if (q < NP) {
-    i = q; j = 0;
-  } else if (q < 2 * NP) {
-    i = q - NP; j = N;
-  } else if (q < 2 * NP + N - 1) {
-    i = 0; j = q - 2 * NP + 1;
-  } else {
-    i = N; j = q - (2 * NP + N - 1) + 1;
-  }
-}
-
-template <int N>
-__host__ __device__ constexpr int n_face_nodes() {
-  return 2 * (N + 1) * (N + 1) + (N - 1) * 4 * N;
-}
-
 template <int N, typename R>
 __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(Cfg<N>::FACE_WAVES))) void k_face_flux(
     const double* __restrict__ U, R* __restrict__ ffv, DevMesh mesh, DevPhys ph, DevBasis basis) {

@@ -36,7 +36,8 @@ hipError_t launch_kinetic_energy_grad(int, const DevMesh&, const double*, const 
 hipError_t launch_triad(const double*, const double*, double, double*, long long, hipStream_t) {
   reached("triad");
 }
-hipError_t launch_metrics(int, const double*, double*, bool, const DevBasis&, long long, int*, hipStream_t) {
+hipError_t launch_metrics(int, const double*, double*, double*, bool, const DevBasis&, long long, int*,
+                          hipStream_t) {
   reached("metrics");
 }
 hipError_t launch_face_flux_curv(int, int, const DevMesh&, const DevPhys&, const DevBasis&, const double*, void*,

@@ -192,7 +192,9 @@ def test_curved_mesh_validation(L):
     L.dg_workspace_bytes(ctx, 0, ctypes.byref(plain))
     L.dg_free(ctx)
     nd = 8 * 64
-    assert size.value >= plain.value + 10 * nd * 8  # metric terms: 10 values per DOF
+    nfn = 2 * (N + 1) ** 2 + (N - 1) * 4 * N  # boundary nodes per element
+    # metric terms: 10 values per DOF, and again per boundary node
+    assert size.value >= plain.value + 10 * nd * 8 + 10 * 8 * nfn * 8
     d, keep = desc()
     st, ctx = _init(L, d, _phys(precision=1))  # mixed precision with the Kennedy-Gruber pair
     assert st == dgsem.DG_OK

@@ -275,7 +275,13 @@ def test_channel_48x32x48_mixed_forward_adjoint_against_fp64():
         os.makedirs(out_dir, exist_ok=True)
         with open(os.path.join(out_dir, "channel_48_adjoint.json"), "w") as f:
             json.dump(res, f, indent=1)
-    assert np.all(e < 1e-3)
+    # mixed forward trajectory: FP32 sweep rounding (~1e-7 relative per stage
+    # in Ut) moves the final state by ~1e-6 relative after 500 steps, and the
+    # FP64 adjoint, linearised about that trajectory, inherits that relative
+    # change; 1e-5 is a decade above the 1.6e-6 measured on the energy
+    bound = 1e-5
+    assert np.all(e < bound), e
+    assert res["J_rel_err_mixed_vs_fp64"] < 1e-9
 
 
 def test_segments_recorded_in_the_forward_pass_give_the_same_gradient():
