@@ -576,9 +576,23 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       if (MIXED)
         ut[4] -= 2.0 * (e_ref * static_cast<double>(ac[0]) + p_ref * static_cast<double>(du));
     }
-    __syncthreads();
+    // The entropy-conserving instances (one workgroup per CU) need no barrier
+    // after the last sweep: P4 reads and writes only the face entries of sX,
+    // which no sweep reads.  (The Kennedy-Gruber ones, two workgroups per CU,
+    // measured slower without it and with the early fetch below.)
+    if (!EC || d < 2) __syncthreads();
   }
 
+  // entropy-conserving instances: G and the own state of the RK update,
+  // fetched now so that their latency overlaps the surface phase
+  double gA[5] = {0, 0, 0, 0, 0}, u0[5] = {0, 0, 0, 0, 0};
+  if (EC && RK && active) {
+    if (st.read_G) {
+#pragma unroll
+      for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
+    }
+    load_state(U, stride, e * NN + tid, u0);
+  }
 
   // P4: surface terms (face lanes); the neighbour index is formed again here
   // rather than held through the sweeps
@@ -731,9 +745,8 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
 
   // P5: surface terms, 1/J, output
   if (active) {
-    double gA[5] = {0, 0, 0, 0, 0};
     const double invJ = KEEP && !MIXED ? static_cast<double>(Jr[9]) : mesh.geo[9 * stride + e * NN + tid];
-    if (RK && st.read_G) {
+    if (!EC && RK && st.read_G) {
 #pragma unroll
       for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
     }
@@ -750,8 +763,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     }
     const long long idx = e * NN + tid;
     if (RK) {
-      double u0[5];
-      load_state(U, stride, idx, u0);  // read again: holding it from P1 spills
+      if (!EC) load_state(U, stride, idx, u0);  // read again: holding it from P1 spills
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double gv = st.A * gA[v] + st.dt * ut[v];
