@@ -102,12 +102,10 @@ typedef struct {
                          two-point fluxes with averaged metrics); the elements
                          keep the structured connectivity of nelem, periodic
                          or isothermal-wall ends (the wall normal is the face's
-                         metric vector); faces may be NULL.  DG_FP64 with either
-                         flux pair (the Roe flux along the face's unit normal,
-                         scaled by its length), DG_MIXED with the
-                         Kennedy-Gruber pair only; DG_MIXED with the
-                         entropy-conserving pair, the wall model and the
-                         adjoint, lifting or kinetic-energy calls give
+                         metric vector); faces may be NULL.  DG_FP64 or DG_MIXED
+                         with either flux pair (the Roe flux along the face's
+                         unit normal, scaled by its length); the wall model
+                         and the adjoint, lifting or kinetic-energy calls give
                          DG_EUNSUPPORTED.  The workspace holds the metric
                          terms, 10 FP64 values per DOF (+ 10 FP32 values in
                          mixed precision) and the FP64 ones again per node

@@ -353,7 +353,6 @@ dg_status dg_init_mesh(const dg_mesh_desc* mesh, const dg_physics* phys, void* h
   }
   if (curved) {
     if (wall_model) return DG_EUNSUPPORTED;
-    if (phys->precision != DG_FP64 && phys->flux == DG_FLUX_EC_ROE) return DG_EUNSUPPORTED;
     const long long n3 = 3 * nE * nn;
     for (long long q = 0; q < n3; ++q)
       if (!std::isfinite(mesh->nodes[q])) return DG_EINVAL;

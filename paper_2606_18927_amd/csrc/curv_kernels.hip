@@ -68,6 +68,42 @@ __device__ inline void ec_flux_contra(const double a[6], const double b[6], doub
   f[4] = F1 * (0.5 / gm1 * inv_beta_ln - 0.5 * q2) + f[1] * u + f[2] * v + f[3] * w;
 }
 
+// The same pair in FP32 relative to the element's reference state (mixed
+// precision): a, b = (rho, u, v, w, beta - beta_ref, |u|^2, pi) with
+// pi = rho (p - p_ref) / p; with sb = beta_a + beta_b,
+//   p^ - p_ref = (pi_a + pi_b) / (2 sb),
+//   1 / beta_ln - 1 / beta_ref = (2 (F - 1) - (dbeta_a + dbeta_b) / beta_ref) / sb,
+// F = atanh f / f of the beta pair (its series less the leading 1 below
+// f^2 = 1e-2), so no FP32 difference of O(p_ref) terms is formed.
+// f = f#_EC - (0, p_ref M, F1 e_ref + p_ref U_c) with U_c = {{u}} . M and
+// e_ref = kap / beta_ref; uc returns U_c.  The p_ref M part sums to the
+// discrete divergence of the metric terms (zero by the metric identities);
+// the energy part is added back in FP64 by the caller.
+__device__ inline void ec_flux_contra_ref(const float a[7], const float b[7], float M0, float M1, float M2,
+                                          float kap, float beta_ref, float ibr, float f[5], float& uc) {
+  const float sr = a[0] + b[0], sdb = a[4] + b[4];
+  const float sb = 2.0f * beta_ref + sdb;
+  const float x = __builtin_amdgcn_rcpf(sr * sb);
+  const float ir = sb * x, ib = sr * x;
+  const float fr = (a[0] - b[0]) * ir, fb = (a[4] - b[4]) * ib;
+  const float ur = fr * fr, ub = fb * fb;
+  float G = 1.0f - ur * (1.0f / 3.0f + ur * (4.0f / 45.0f + ur * (44.0f / 945.0f)));
+  float Fs = ub * (1.0f / 3.0f + ub * (0.2f + ub * (1.0f / 7.0f)));
+  if (ur >= 1e-2f) G = fr / atanhf(fr);
+  if (ub >= 1e-2f) Fs = atanhf(fb) / fb - 1.0f;
+  const float u = 0.5f * (a[1] + b[1]), v = 0.5f * (a[2] + b[2]), w = 0.5f * (a[3] + b[3]);
+  uc = u * M0 + v * M1 + w * M2;
+  const float F1 = 0.5f * sr * G * uc;
+  const float dp = 0.5f * (a[6] + b[6]) * ib;
+  const float dib = (2.0f * Fs - sdb * ibr) * ib;
+  const float X = kap * dib - 0.25f * (a[5] + b[5]) + (u * u + v * v + w * w);
+  f[0] = F1;
+  f[1] = F1 * u + dp * M0;
+  f[2] = F1 * v + dp * M1;
+  f[3] = F1 * w + dp * M2;
+  f[4] = F1 * X + dp * uc;
+}
+
 // Roe's dissipation sum_k |lambda_k| alpha_k r_k across a face with unit
 // normal n (L on the side n points away from; primitives (rho, u, v, w, p)
 // and total energies E), linearised at the Roe average (sqrt(rho)-weighted u
@@ -352,27 +388,33 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) void k_face_flux_curv(const double*
 
 // ------------------------------------------------------- right-hand side / RK
 // The Kennedy-Gruber instances fit 128 registers (four waves per SIMD); the
-// entropy-conserving ones are bounded for three: at 128 they spilled 46-58
-// values per lane, and at degree 7 one workgroup per CU without spills is 17 %
-// faster than two with them.
-// R = float: mixed precision (Kennedy-Gruber pair only): the LDS fields,
-// gradients, metric terms of the sweeps and line sums in FP32, with p, e and T
-// relative to the element's first node; primitive recovery, lifting
-// corrections, surface fluxes, 1/J scaling and the RK update in FP64.  The
-// reference pressure's share of the momentum sums is the discrete divergence
-// of the metric terms (zero by the metric identities) and is dropped; the
-// energy's, e_ref sum D (rho U~)# + p_ref sum D U~#, is added back in FP64.
+// FP64 entropy-conserving ones are bounded for three: at 128 they spilled
+// 46-58 values per lane, and at degree 7 one workgroup per CU without spills
+// is 17 % faster than two with them.  The mixed-precision entropy-conserving
+// ones are bounded for four (degree 7: 6 values spilled, 1.85 ms against
+// 2.63 ms with three waves and no spills).
+// R = float: mixed precision: the LDS fields, gradients, metric terms of the
+// sweeps and line sums in FP32, with p, e and T (entropy-conserving pair:
+// beta and rho (p - p_ref) / p) relative to the element's first node;
+// primitive recovery, lifting corrections, surface fluxes, 1/J scaling and
+// the RK update in FP64.  The reference pressure's share of the momentum sums
+// is the discrete divergence of the metric terms (zero by the metric
+// identities) and is dropped; the energy's, e_ref sum D (rho U~)# + p_ref sum
+// D U~#, is added back in FP64.
 template <int N, typename R, bool RK, bool VISC, bool EC>
-__global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(EC ? 3 : 4))) void k_rhs_curv(
+__global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(EC && sizeof(R) == sizeof(double) ? 3 : 4))) void k_rhs_curv(
     const double* __restrict__ U, const R* __restrict__ ffv, double* __restrict__ out,
     double* __restrict__ U_out, DevMesh mesh, DevPhys ph, DevBasis basis, Stage st,
     int* __restrict__ status) {
   using C = CurvCfg<N>;
   constexpr int NP = C::NP, NF = C::NF, NN = C::NN;
   constexpr bool MIXED = sizeof(R) == sizeof(float);
-  static_assert(!(EC && MIXED), "the entropy-conserving pair on curved elements is FP64 only");
+  // LDS fields per node: rho, u, v, w, p, e (p, e relative to the reference in
+  // mixed precision); entropy-conserving pair: rho, u, v, w, beta, |u|^2, in
+  // mixed precision beta - beta_ref and, seventh, rho (p - p_ref) / p
+  constexpr int NSP = EC && MIXED ? 7 : 6;
   __shared__ double sD[NP][N + 2];
-  __shared__ R sp[6][NN];                 // rho, u, v, w, p, e (p, e relative to the reference if MIXED)
+  __shared__ R sp[NSP][NN];
   __shared__ double sX[6][5][NF];         // own viscous face flux, then surface terms
   // phase-shared regions: (T, lifting terms) until the gradients are formed,
   // (viscous flux, metric of the sweep direction) in the sweeps
@@ -397,7 +439,9 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   // P1: own state; face lanes fetch the neighbour's face node (registers are
   // the limit of this kernel: metric terms, the neighbour's state and the own
   // primitives are fetched again where they are used, from L2 and LDS)
-  double p_ref = 0.0, e_ref = 0.0, T_ref = 0.0;  // mixed precision: the element's first node
+  // mixed precision: the element's first node (with the entropy-conserving
+  // pair e_ref is its internal energy p_ref / ((gamma - 1) rho_ref))
+  double p_ref = 0.0, e_ref = 0.0, T_ref = 0.0, beta_ref = 0.0;
   if (active) {
     double u0[5];
     load_state(U, stride, e * NN + tid, u0);
@@ -408,15 +452,17 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       load_state(U, stride, e * NN, s0);
       const Prim P0 = primitives(s0, ph);
       p_ref = P0.p;
-      e_ref = P0.e;
+      e_ref = EC ? P0.p / (ph.gm1 * P0.rho) : P0.e;
       T_ref = P0.T;
+      beta_ref = 0.5 * P0.rho / P0.p;
     }
     sp[0][tid] = static_cast<R>(P.rho);
     sp[1][tid] = static_cast<R>(P.u);
     sp[2][tid] = static_cast<R>(P.v);
     sp[3][tid] = static_cast<R>(P.w);
-    sp[4][tid] = static_cast<R>(EC ? 0.5 * P.rho / P.p : P.p - p_ref);
+    sp[4][tid] = static_cast<R>(EC ? 0.5 * P.rho / P.p - beta_ref : P.p - p_ref);
     sp[5][tid] = static_cast<R>(EC ? P.u * P.u + P.v * P.v + P.w * P.w : P.e - e_ref);
+    if constexpr (EC && MIXED) sp[NSP - 1][tid] = static_cast<R>(P.rho * (P.p - p_ref) / P.p);
     if (VISC) sT[tid] = static_cast<R>(P.T - T_ref);
   }
   double sn[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
@@ -491,7 +537,9 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   for (int d = 0; d < 3; ++d) {
     const int idx = d == 0 ? i : (d == 1 ? j : k);
     const int ab = d == 0 ? j + NP * k : (d == 1 ? i + NP * k : i + NP * j);
-    R M0 = 0, M1 = 0, M2 = 0, A[6] = {1, 0, 0, 0, 1, 1};
+    R M0 = 0, M1 = 0, M2 = 0, A[NSP];
+#pragma unroll
+    for (int c = 0; c < NSP; ++c) A[c] = R(c == 0 || c == 4 || c == 5 ? 1 : 0);
     if (active) {
       const long long gi = e * NN + tid;
       if (KEEP) {
@@ -504,7 +552,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
         M2 = geo_at<R>(mesh.geo, stride, 3 * d + 2, gi);
       }
 #pragma unroll
-      for (int c = 0; c < 6; ++c) A[c] = sp[c][tid];
+      for (int c = 0; c < NSP; ++c) A[c] = sp[c][tid];
       sM[0][tid] = M0;
       sM[1][tid] = M1;
       sM[2][tid] = M2;
@@ -525,7 +573,28 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       const int base = d == 0 ? NP * (j + NP * k) : (d == 1 ? i + NF * k : i + NP * j);
       const int step = d == 0 ? 1 : (d == 1 ? NP : NF);
       R ac[5] = {0, 0, 0, 0, 0}, av[4] = {0, 0, 0, 0}, du = 0;
-      if constexpr (EC) {
+      if constexpr (EC && MIXED) {
+        const float kap = static_cast<float>(0.5 / ph.gm1), br = static_cast<float>(beta_ref),
+                    ibr = static_cast<float>(1.0 / beta_ref);
+#pragma unroll 1
+        for (int m = 0; m < NP; ++m) {
+          const int nm = base + step * m;
+          const float Dm = static_cast<float>(sD[idx][m]);
+          const float m0 = 0.5f * (M0 + sM[0][nm]), m1 = 0.5f * (M1 + sM[1][nm]), m2 = 0.5f * (M2 + sM[2][nm]);
+          float B[NSP];
+#pragma unroll
+          for (int c = 0; c < NSP; ++c) B[c] = sp[c][nm];
+          float f[5], uc;
+          ec_flux_contra_ref(A, B, m0, m1, m2, kap, br, ibr, f, uc);
+#pragma unroll
+          for (int v = 0; v < 5; ++v) ac[v] += Dm * f[v];
+          du += Dm * uc;
+          if (VISC) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) av[c] += Dm * sfv[c][nm];
+          }
+        }
+      } else if constexpr (EC) {
         // not unrolled: the pair flux is long, and unrolled copies keep too
         // many values live
 #pragma unroll 1
@@ -628,10 +697,24 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     const Prim Pn = primitives(sn, ph);
     double Fo[5], Fs[5], vo[3];  // own contravariant Euler flux, surface flux, own velocity
     if constexpr (EC) {
-      // sp holds (rho, u, v, w, beta, |u|^2): p = rho / (2 beta), E from p and |u|^2
-      const double A6[6] = {sp[0][lo], sp[1][lo], sp[2][lo], sp[3][lo], sp[4][lo], sp[5][lo]};
-      const double po = 0.5 * A6[0] / A6[4];
-      const double Eo = po / ph.gm1 + 0.5 * A6[0] * A6[5];
+      // FP64: sp holds (rho, u, v, w, beta, |u|^2): p = rho / (2 beta), E from p
+      // and |u|^2; mixed precision: the own face node in FP64, from U
+      double A6[6], po, Eo;
+      if constexpr (MIXED) {
+        double s5[5];
+        load_state(U, stride, e * NN + lo, s5);
+        const Prim Po = primitives(s5, ph);
+        A6[0] = Po.rho; A6[1] = Po.u; A6[2] = Po.v; A6[3] = Po.w;
+        A6[4] = 0.5 * Po.rho / Po.p;
+        A6[5] = Po.u * Po.u + Po.v * Po.v + Po.w * Po.w;
+        po = Po.p;
+        Eo = s5[4];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) A6[c] = sp[c][lo];
+        po = 0.5 * A6[0] / A6[4];
+        Eo = po / ph.gm1 + 0.5 * A6[0] * A6[5];
+      }
       vo[0] = A6[1];
       vo[1] = A6[2];
       vo[2] = A6[3];
@@ -810,7 +893,16 @@ hipError_t rhs_curv_n(const DevMesh& m, const DevPhys& p, const DevBasis& b, con
       return hipGetLastError();
     }
   } else {
-    if (p.ec) return hipErrorInvalidValue;  // rejected at init: FP64 only on curved elements
+    if (p.ec) {
+      if (!p.mixed_ref) return hipErrorInvalidValue;  // rejected at init: needs the reference state
+      if (p.viscous)
+        hipLaunchKernelGGL((k_rhs_curv<N, R, RK, true, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b,
+                           st, status);
+      else
+        hipLaunchKernelGGL((k_rhs_curv<N, R, RK, false, true>), grid, block, 0, s, U, ffv, out, U_out, m, p, b,
+                           st, status);
+      return hipGetLastError();
+    }
   }
   if (p.viscous)
     hipLaunchKernelGGL((k_rhs_curv<N, R, RK, true, false>), grid, block, 0, s, U, ffv, out, U_out, m, p, b, st,

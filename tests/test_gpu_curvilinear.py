@@ -322,10 +322,6 @@ def test_curved_rejected_combinations():
     need_gpu()
     N = 3
     X = _warped(N, (2, 2, 2), 0.05)
-    for kw in (dict(precision="mixed", flux="ec_roe"),):
-        with pytest.raises(dgsem.DgsemError) as ei:
-            _solver(N, X, GAS, **kw)
-        assert ei.value.status == dgsem.DG_EUNSUPPORTED
     spec = dgsem.MeshSpec(N, None, ("periodic", "wallmodel", "periodic"), nodes=X)
     with pytest.raises(dgsem.DgsemError) as ei:
         dgsem.Solver(spec, 1.4, 1.0, 0.02, 0.72)
