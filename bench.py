@@ -20,7 +20,8 @@ paper's PID (Eq. 1) with one GPU; lower is better.  Also reported:
                 Roe surface flux (FP64);
   sutherland    the same step with Sutherland's viscosity law (FP64);
   curved        the same step on curved elements (the periodic box warped by
-                5 %, FP64): per-node metric terms, contravariant fluxes;
+                5 %): per-node metric terms, contravariant fluxes; FP64 and
+                mixed precision, each flux pair;
   wall_model    the N = 5, 48x32x48 channel with wall-modelled slip walls and
                 Sutherland's law (FP64) beside the same channel with
                 isothermal walls and constant viscosity, and the wall-stress
@@ -598,6 +599,11 @@ def main():
                                                    "rk_traffic_over_algorithmic")}
             print(f"[bench] curved mixed {cmx['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage", file=sys.stderr,
                   flush=True)
+            cem = run_curved(args.steps, args.warmup, flux="ec_roe", precision="mixed")
+            curved["ec_roe"]["mixed"] = {k: cem[k] for k in ("ns_per_dof_stage", "ms_per_step", "rk_kernel_ms",
+                                                             "face_kernel_ms", "step_frac")}
+            print(f"[bench] curved ec_roe mixed {cem['ns_per_dof_stage']*1e3:.1f} ps/DOF/stage",
+                  file=sys.stderr, flush=True)
         except dgsem.DgsemError as e:
             curved = {"error": str(e)}
     small = None
