@@ -658,7 +658,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
   if (EC && RK && active) {
     if (st.read_G) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
+      for (int v = 0; v < 5; ++v) gA[v] = load_once(&out[v * stride + e * NN + tid]);
     }
     load_state(U, stride, e * NN + tid, u0);
   }
@@ -813,7 +813,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
       } else {
         const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) fvs[c] = 0.5 * (fvo[c] + static_cast<double>(src[c * NF]));
+        for (int c = 0; c < 4; ++c) fvs[c] = 0.5 * (fvo[c] + static_cast<double>(load_once(&src[c * NF])));
       }
     }
     const double sc = ft.up ? basis.inv_w_end : -basis.inv_w_end;
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
     const double invJ = KEEP && !MIXED ? static_cast<double>(Jr[9]) : mesh.geo[9 * stride + e * NN + tid];
     if (!EC && RK && st.read_G) {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) gA[v] = out[v * stride + e * NN + tid];
+      for (int v = 0; v < 5; ++v) gA[v] = load_once(&out[v * stride + e * NN + tid]);
     }
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
@@ -850,12 +850,12 @@ __global__ __launch_bounds__(CurvCfg<N>::BS) __attribute__((amdgpu_waves_per_eu(
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double gv = st.A * gA[v] + st.dt * ut[v];
-        out[v * stride + idx] = gv;
-        U_out[v * stride + idx] = u0[v] + st.B * gv;
+        store_once(&out[v * stride + idx], gv);
+        store_once(&U_out[v * stride + idx], u0[v] + st.B * gv);
       }
     } else {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) out[v * stride + idx] = ut[v];
+      for (int v = 0; v < 5; ++v) store_once(&out[v * stride + idx], ut[v]);
     }
   }
 }

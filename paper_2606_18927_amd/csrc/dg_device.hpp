@@ -226,6 +226,20 @@ __device__ inline double viscosity_ratio(const DevPhys& ph, double T) {
 
 __device__ inline double vel(const Prim& P, int d) { return d == 0 ? P.u : (d == 1 ? P.v : P.w); }
 
+// Values a kernel reads or writes once (G, the neighbours' face viscous
+// fluxes, the updated state): non-temporal accesses, so that they do not
+// displace from L2 the states that neighbouring workgroups read.  Only for
+// whole coalesced rows: the scattered face-flux stores of the face kernels
+// were slower non-temporal (no write combining in L2).
+template <typename T>
+__device__ inline T load_once(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ inline void store_once(T* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
+
 __device__ inline void load_state(const double* U, long long stride, long long idx, double u[5]) {
 #pragma unroll
   for (int v = 0; v < 5; ++v) u[v] = U[v * stride + idx];

@@ -1099,12 +1099,13 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
         _Pragma("unroll") for (int c = 0; c < 4; ++c) sX[le][2 * D + 1][c][ab] = fv[c];     \
     }                                                                                       \
     if constexpr (D == 2 && EARLY) {                                                        \
-      if (RK && active && st.read_G) load_state(out, stride, e * NN + node, gA);            \
+      if (RK && active && st.read_G)                                                        \
+        _Pragma("unroll") for (int v = 0; v < 5; ++v) gA[v] = load_once(&out[v * stride + e * NN + node]); \
       if (VISC && face_ok && !fwall) {                                                      \
         const FaceTask<N> ft(tid);                                                          \
         const long long nb = neighbour(mesh, ex0, ey0, ez0, ft.d, ft.up);                   \
         const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;             \
-        _Pragma("unroll") for (int c = 0; c < 4; ++c) fvn_pre[c] = static_cast<double>(src[c * NF]); \
+        _Pragma("unroll") for (int c = 0; c < 4; ++c) fvn_pre[c] = static_cast<double>(load_once(&src[c * NF])); \
       }                                                                                     \
     }                                                                                       \
     __syncthreads();                                                                        \
@@ -1145,7 +1146,9 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #undef DG_DIRECTION
 
   if (!EARLY || !VISC) {  // (Euler with the Kennedy-Gruber pair: no sweeps in P3)
-    if (RK && active && st.read_G) load_state(out, stride, e * NN + node, gA);
+    if (RK && active && st.read_G)
+#pragma unroll
+      for (int v = 0; v < 5; ++v) gA[v] = load_once(&out[v * stride + e * NN + node]);
   }
 
   // ---- P4: surface corrections (face lanes, FP64) -----------------------
@@ -1159,7 +1162,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     if (!EARLY && VISC && !fwall) {
       const R* src = ffv + nb * (6 * 4 * NF) + ((ft.f ^ 1) * 4) * NF + ft.ab;
 #pragma unroll
-      for (int c = 0; c < 4; ++c) fvn[c] = static_cast<double>(src[c * NF]);
+      for (int c = 0; c < 4; ++c) fvn[c] = static_cast<double>(load_once(&src[c * NF]));
     }
     double A[6], so[5], sn[5], q2o = 0.0;
     if (MIXED) {
@@ -1273,14 +1276,14 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
 #pragma unroll
       for (int v = 0; v < 5; ++v) {
         const double gv = st.A * gA[v] + st.dt * ut[v];
-        out[v * stride + idx] = gv;
+        store_once(&out[v * stride + idx], gv);
         // the entropy-conserving instance reads U again here: holding it
         // from the first phase spills its registers (6 % slower)
-        U_out[v * stride + idx] = (EC ? U[v * stride + idx] : u0[v]) + st.B * gv;
+        store_once(&U_out[v * stride + idx], (EC ? U[v * stride + idx] : u0[v]) + st.B * gv);
       }
     } else {
 #pragma unroll
-      for (int v = 0; v < 5; ++v) out[v * stride + idx] = ut[v];
+      for (int v = 0; v < 5; ++v) store_once(&out[v * stride + idx], ut[v]);
     }
   }
 }
