@@ -626,10 +626,10 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
     for (int x = 0; x < 3; ++x)
 #pragma unroll
       for (int y = 0; y < 3; ++y)
-        gbar[(3 * x + y) * stride + idx] =
-            mu * (tb[3 * x + y] + tb[3 * y + x]) - (x == y ? (2.0 / 3.0) * mu * tr : 0.0);
+        store_once(&gbar[(3 * x + y) * stride + idx],
+                   mu * (tb[3 * x + y] + tb[3 * y + x]) - (x == y ? (2.0 / 3.0) * mu * tr : 0.0));
 #pragma unroll
-    for (int d = 0; d < 3; ++d) gbar[(9 + d) * stride + idx] = gT[d];
+    for (int d = 0; d < 3; ++d) store_once(&gbar[(9 + d) * stride + idx], gT[d]);
   }
   // Sutherland's law: tau and q scale with r(T), so T gets
   // (d ln r / dT) (tbar : tau + sum_d Fv_d,E q_d), d ln r / dT = 3 / (2 T) - 1 / (T + S)
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(Cfg<N>::BS) __attribute__((amdgpu_waves_per_eu(4)))
   load_state(U, stride, idx, s);
   prim_vjp(s, Pb, Tb, ph, Ub);
 #pragma unroll
-  for (int v = 0; v < 5; ++v) ubar[v * stride + idx] = Ub[v];
+  for (int v = 0; v < 5; ++v) store_once(&ubar[v * stride + idx], Ub[v]);
 }
 
 // --------------------------------------------------------------------------
@@ -724,7 +724,8 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_b(const double* __restrict__
   if (EPB > 1) elem_coords(e, mesh, ex, ey, ez);
   const long long idx = e * NN + node;
   double Ub[5];
-  load_state(ubar, stride, idx, Ub);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) Ub[v] = load_once(&ubar[v * stride + idx]);
   if (visc) {
     const double sx = mesh.s[0][ex], sy = mesh.s[1][ey], sz = mesh.s[2][ez];
     double qb[4];
@@ -755,13 +756,13 @@ __global__ __launch_bounds__(Cfg<N>::BS) void k_vjp_b(const double* __restrict__
     // cot <- cot_a cot + cot_b out at this node (no workgroup reads cot here)
 #pragma unroll
     for (int v = 0; v < 5; ++v) {
-      const double nv = out[v * stride + idx] + scale * Ub[v];
-      out[v * stride + idx] = nv;
-      if (cot) cot[v * stride + idx] = cot_a * cot[v * stride + idx] + cot_b * nv;
+      const double nv = load_once(&out[v * stride + idx]) + scale * Ub[v];
+      store_once(&out[v * stride + idx], nv);
+      if (cot) store_once(&cot[v * stride + idx], cot_a * load_once(&cot[v * stride + idx]) + cot_b * nv);
     }
   } else {
 #pragma unroll
-    for (int v = 0; v < 5; ++v) out[v * stride + idx] = Ub[v];
+    for (int v = 0; v < 5; ++v) store_once(&out[v * stride + idx], Ub[v]);
   }
 }
 
@@ -771,8 +772,8 @@ __global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, do
                         long long n) {
   for (long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; t < n;
        t += static_cast<long long>(gridDim.x) * blockDim.x) {
-    const double ay = a == 0.0 ? 0.0 : a * y[t];
-    y[t] = x ? ay + b * x[t] : ay;
+    const double ay = a == 0.0 ? 0.0 : a * load_once(&y[t]);
+    store_once(&y[t], x ? ay + b * load_once(&x[t]) : ay);
   }
 }
 
