@@ -80,22 +80,23 @@ ALG_FLOPS_PER_DOF_STAGE = 940.0
 # FP64 flops per DOF and stage counted with rocprofv3 (SQ_INSTS_VALU_{ADD,MUL,
 # FMA,TRANS}_F64 x 64 lanes, FMA twice) on k_rhs + k_face_flux of this
 # workload; valid only for the kernel sources they were counted on.
-COUNTED_FLOPS = {"sources_sha256_prefix": "dfaa36e09b1578e5", "per_dof_stage": 1323.0 + 219.0}
+COUNTED_FLOPS = {"sources_sha256_prefix": "d24ddbf48a2f0125", "per_dof_stage": 1302.25 + 219.375}
 
 # HBM bytes per launch of k_rhs<7,double> on this workload, from rocprofv3
 # counter passes (profiles/k_rhs_k_face_flux_tgv_n7_32x32x32.md): reads
-# 128 x 14,212,096.9 TCC_EA0_RDREQ_128B + 64 x 2,529.0 RDREQ_64B, writes
-# WRITE_SIZE 1,310,720 KiB.  Valid only for the kernel sources it was counted
-# on; reported as null once they change.
-COUNTED_TRAFFIC = {"sources_sha256_prefix": "dfaa36e09b1578e5", "bytes_per_launch": 3161487541.0}
+# 128 x 13,968,395.1 TCC_EA0_RDREQ_128B + 64 x 2,077.0 RDREQ_64B, writes
+# WRITE_SIZE 1,310,764.8 KiB.  Valid only for the kernel sources it was
+# counted on; reported as null once they change.
+COUNTED_TRAFFIC = {"sources_sha256_prefix": "d24ddbf48a2f0125", "bytes_per_launch": 3130310656.0}
 TRAFFIC_SOURCES = ("fwd_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 # The same for k_rhs_curv<7,double,true,true,false> on the curved workload
 # (profiles/k_rhs_curv_k_face_flux_curv_tgv_n7_32x32x32_curved.md): reads
-# 128 x 47,179,152.3 RDREQ_128B + 64 x 2,081.0 RDREQ_64B, writes 1,310,720 KiB;
+# 128 x 35,124,061.3 RDREQ_128B + 64 x 1,876.9 RDREQ_64B, writes 1,310,738.8 KiB;
 # and for its mixed-precision instance k_rhs_curv<7,float,true,true,false>:
-# reads 128 x 34,049,318.5 RDREQ_128B + 64 x 6,760.8 RDREQ_64B, same writes.
-COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "fe7ab567a73f99a8", "bytes_per_launch": 7381241954.0}
-COUNTED_TRAFFIC_CURVED_MIXED = {"sources_sha256_prefix": "fe7ab567a73f99a8", "bytes_per_launch": 5700922735.0}
+# reads 128 x 27,055,205.1 RDREQ_128B + 64 x 4,193.1 RDREQ_64B, writes
+# 1,310,720.3 KiB.
+COUNTED_TRAFFIC_CURVED = {"sources_sha256_prefix": "f059d7093f7e0d5b", "bytes_per_launch": 5838196499.0}
+COUNTED_TRAFFIC_CURVED_MIXED = {"sources_sha256_prefix": "f059d7093f7e0d5b", "bytes_per_launch": 4805512198.0}
 TRAFFIC_SOURCES_CURVED = ("curv_kernels.hip", "dg_device.hpp", "dg_internal.hpp")
 
 
